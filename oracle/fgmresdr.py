@@ -1,0 +1,207 @@
+"""Flexible GMRES with deflated restarts (FGMRES-DR), FP64 NumPy oracle.
+
+Test infrastructure only. Follows the paper's Section 4:
+  * flexible Arnoldi process (Alg. 3) with modified Gram-Schmidt as
+    written there, keeping the preconditioned vectors z_j = M_j v_j;
+  * flexible Arnoldi relation A Z_m = V_{m+1} H^_m and the small least
+    squares problem for the iterate (Section 4.2);
+  * harmonic Ritz pairs from H_m + f_m h_m^H with H_m^H f_m = h_m
+    (Lemma 1a) and the deflated restart of Section 4.4: G_{k+1} built from
+    the k Ritz vectors of smallest-modulus harmonic Ritz values and the
+    small residual c - H^ eta, its QR factorisation, H^_k = Q^H H^ Q_k,
+    V_{k+1} = V Q_{k+1}, Z_k = Z Q_k (Alg. 4 and Section 4.5);
+  * explicit FP64 residual once per cycle, injected into the right-hand
+    side c = [V_{k+1}^H r; 0], and a clean restart (no deflation) when
+    ||r_explicit|| / ||r_implicit|| > t (Section 4.7).
+
+Readings taken where the paper is silent:
+  * m is the total basis size including the k deflation vectors; cycles
+    after the first perform m - k new Arnoldi steps;
+  * one iteration = one flexible Arnoldi step (one M and one A product);
+  * x0 = 0; the solve stops when the explicit residual satisfies
+    ||b - A x|| <= tol ||b||; a cycle ends early once the implicit residual
+    (from the small least-squares problem) reaches tol ||b||;
+  * h_{j+1,j} <= 1e-14 ||H^|| is a breakdown that ends the cycle;
+  * a singular H_m, a cycle too short to deflate (fewer than k + 1 steps)
+    or a non-finite value leads to a clean restart;
+  * harmonic Ritz values are ordered by modulus with a stable sort.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.linalg
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    converged: bool
+    iterations: int
+    cycles: int
+    clean_restarts: int
+    true_relres: float
+    implicit_relres: float
+    history: list            # (iteration, implicit relative residual) per Arnoldi step
+    cycle_ends: list         # (iteration, explicit relative residual) per cycle
+    ritz_values: np.ndarray  # harmonic Ritz values of the last restart (sorted by modulus)
+
+
+def _lsq(H, c):
+    """eta = argmin ||c - H eta||; returns (eta, ||c - H eta||)."""
+    eta = np.linalg.lstsq(H, c, rcond=None)[0]
+    return eta, float(np.linalg.norm(c - H @ eta))
+
+
+def harmonic_ritz(Hhat):
+    """Harmonic Ritz pairs from H^ = [H_m; h_m^H] (Lemma 1a).
+
+    Returns (lam, G) sorted by |lam| ascending (stable), eigenvectors in the
+    columns of G.
+    """
+    mm = Hhat.shape[1]
+    Hm = Hhat[:mm, :]
+    hrow = Hhat[mm, :]                       # this row is h_m^H
+    f = np.linalg.solve(Hm.conj().T, hrow.conj())  # H_m^H f = h_m
+    lam, G = scipy.linalg.eig(Hm + np.outer(f, hrow))
+    order = np.argsort(np.abs(lam), kind="stable")
+    return lam[order], G[:, order]
+
+
+def flexible_arnoldi(A, M, b, m):
+    """Alg. 3: m steps from v_1 = b/||b||. Returns (V, Z, H)."""
+    n = b.size
+    V = np.zeros((n, m + 1), dtype=np.complex128)
+    Z = np.zeros((n, m), dtype=np.complex128)
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    V[:, 0] = b / np.linalg.norm(b)
+    for j in range(m):
+        Z[:, j] = M(V[:, j])
+        w = A(Z[:, j])
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[:, i], w)
+            w = w - H[i, j] * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+    return V, Z, H
+
+
+def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
+             breakdown_tol=1e-14, keep_basis=False):
+    """Solve A x = b by FGMRES-DR(m, k) (Alg. 4) from x0 = 0.
+
+    A, M: callables on flat complex vectors. M may change from call to call
+    (flexible preconditioning). Returns (x, SolveInfo) and, with
+    ``keep_basis``, also (V, Z, H^) of the last cycle, cut to the steps
+    that cycle performed.
+    """
+    if not (0 <= k < m):
+        raise ValueError("need 0 <= k < m")
+    b = np.asarray(b, dtype=np.complex128).reshape(-1)
+    n = b.size
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros(n, dtype=np.complex128)
+    r = b.copy()
+    V = np.zeros((n, m + 1), dtype=np.complex128)
+    Z = np.zeros((n, m), dtype=np.complex128)
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    c = np.zeros(m + 1, dtype=np.complex128)
+    iters = cycles = clean = 0
+    history, cycle_ends = [], []
+    ritz = np.zeros(0, dtype=np.complex128)
+    fresh = True
+    res_e = bnorm
+    res_i = bnorm
+    if bnorm == 0.0:
+        return x, SolveInfo(True, 0, 0, 0, 0.0, 0.0, [], [], ritz)
+
+    while True:
+        if fresh:
+            beta = float(np.linalg.norm(r))
+            V[:] = 0.0
+            Z[:] = 0.0
+            H[:] = 0.0
+            c[:] = 0.0
+            V[:, 0] = r / beta
+            c[0] = beta
+            j0 = 0
+        else:
+            j0 = k
+        jend = j0
+        broke = False
+        # flexible Arnoldi steps j0 .. m-1 (0-based column index)
+        for j in range(j0, m):
+            Z[:, j] = M(V[:, j])
+            w = A(Z[:, j])
+            iters += 1
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[:, i], w)
+                w = w - H[i, j] * V[:, i]
+            H[j + 1, j] = np.linalg.norm(w)
+            jend = j + 1
+            hnorm = np.linalg.norm(H[:j + 2, :j + 1])
+            broke = bool(abs(H[j + 1, j]) <= breakdown_tol * hnorm)
+            if not broke:
+                V[:, j + 1] = w / H[j + 1, j]
+            _, ri = _lsq(H[:j + 2, :j + 1], c[:j + 2])
+            history.append((iters, ri / bnorm))
+            if broke or ri <= tol * bnorm or iters >= max_iter:
+                break
+        # iterate and explicit residual for this cycle
+        Hc = H[:jend + 1, :jend]
+        eta, res_i = _lsq(Hc, c[:jend + 1])
+        x = x + Z[:, :jend] @ eta
+        r = b - A(x)
+        res_e = float(np.linalg.norm(r))
+        cycles += 1
+        cycle_ends.append((iters, res_e / bnorm))
+        if res_e <= tol * bnorm:
+            return _finish(x, True, iters, cycles, clean, res_e, res_i, bnorm,
+                           history, cycle_ends, ritz, keep_basis, V, Z, H, jend)
+        if iters >= max_iter:
+            return _finish(x, False, iters, cycles, clean, res_e, res_i, bnorm,
+                           history, cycle_ends, ritz, keep_basis, V, Z, H, jend)
+        if k == 0:
+            fresh = True          # plain restarted FGMRES(m)
+            continue
+        # clean restart when explicit and implicit residual disagree (Section 4.7)
+        if broke or jend <= k or res_e > t_clean * max(res_i, 1e-300):
+            clean += 1
+            fresh = True
+            continue
+        # deflated restart (Section 4.4/4.5)
+        try:
+            lam, G = harmonic_ritz(Hc)
+        except np.linalg.LinAlgError:
+            clean += 1
+            fresh = True
+            continue
+        if not np.all(np.isfinite(lam)) or not np.all(np.isfinite(G)):
+            clean += 1
+            fresh = True
+            continue
+        ritz = lam
+        Gk1 = np.zeros((jend + 1, k + 1), dtype=np.complex128)
+        Gk1[:jend, :k] = G[:, :k]
+        Gk1[:, k] = c[:jend + 1] - Hc @ eta
+        Q, _ = np.linalg.qr(Gk1)
+        Qk = Q[:jend, :k]
+        Hk = Q.conj().T @ Hc @ Qk
+        V[:, :k + 1] = V[:, :jend + 1] @ Q
+        Z[:, :k] = Z[:, :jend] @ Qk
+        V[:, k + 1:] = 0.0
+        Z[:, k:] = 0.0
+        H[:] = 0.0
+        H[:k + 1, :k] = Hk
+        c[:] = 0.0
+        c[:k + 1] = V[:, :k + 1].conj().T @ r
+        fresh = False
+
+
+def _finish(x, conv, iters, cycles, clean, res_e, res_i, bnorm, history,
+            cycle_ends, ritz, keep_basis, V, Z, H, jend):
+    info = SolveInfo(conv, iters, cycles, clean, res_e / bnorm, res_i / bnorm,
+                     history, cycle_ends, ritz)
+    if keep_basis:
+        return x, info, (V[:, :jend + 1], Z[:, :jend], H[:jend + 1, :jend])
+    return x, info
