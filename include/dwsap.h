@@ -1,0 +1,185 @@
+/*
+ * dwsap.h -- C ABI of the MI355X (gfx950) SAP-preconditioned FGMRES-DR
+ * solver for the Wilson-Dirac operator.
+ *
+ * Method: A. Frommer, A. Nobile, P. Zingler, "Deflation and Flexible
+ * SAP-Preconditioning of GMRES in Lattice QCD Simulation", arXiv:1204.5463.
+ * The library solves D x = b (Section 2) with flexible GMRES with deflated
+ * restarts (Section 4, Alg. 4), right-preconditioned by the Schwarz
+ * alternating procedure (Section 2, Alg. 2) whose block systems are solved
+ * approximately by a fixed number of minimal-residual steps (Sections 3, 5).
+ *
+ * Operator (eq. 1, mass normalisation, periodic in all four directions):
+ *   (D x)(n) = (4 + m0) x(n)
+ *      - 1/2 sum_mu [ (1 - g_mu) U_mu(n) x(n+mu) + (1 + g_mu) U_mu(n-mu)^+ x(n-mu) ]
+ * The paper's hopping-parameter form corresponds to kappa = 1/(2 (4 + m0)).
+ * Gamma matrices: Euclidean chiral basis g_k = [[0, -i s_k], [i s_k, 0]]
+ * (k = x, y, z), g_t = [[0, 1], [1, 0]].
+ *
+ * Conventions for every call:
+ *   - Return value: dw_status, DW_OK (0) on success, a negative code on
+ *     failure; dw_last_error() gives the calling thread's last message.
+ *     No C++ exception crosses this interface.
+ *   - Lattice extents L[4] = {Lx, Ly, Lz, Lt}; direction mu = 0..3 is
+ *     x, y, z, t. Canonical site index n = x + Lx*(y + Ly*(z + Lz*t)).
+ *   - Caller buffers are DEVICE pointers to complex128 numbers stored as
+ *     interleaved (re, im) doubles:
+ *       spinor fields [rhs][n][spin 4][colour 3]  (12 complex per site),
+ *       gauge fields  [mu][n][a 3][b 3]           (U_mu(n)_{ab}).
+ *     Caller buffers stay owned by the caller; the library never frees or
+ *     retains them after a call returns (server requests excepted).
+ *   - Streams: every call enqueues its work on the given HIP stream and is
+ *     asynchronous unless stated otherwise. Device memory that the library
+ *     needs comes from the context's allocator.
+ */
+#ifndef DWSAP_H
+#define DWSAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dw_status;
+enum {
+  DW_OK = 0,
+  DW_EINVAL = -1,    /* invalid argument: geometry, parameters, null pointer */
+  DW_ENOMEM = -2,    /* device allocation failed */
+  DW_EHIP = -3,      /* a HIP runtime call failed */
+  DW_ENOTCONV = -4,  /* solver stopped at max_iter; x holds the last iterate */
+  DW_EBUSY = -5,     /* server queue full / request not finished */
+  DW_ENOTFOUND = -6  /* unknown server ticket */
+};
+
+/* Storage precision of the SAP preconditioner's fields (links and
+ * spinors). Arithmetic is FP32 for F32/F16/BF16 storage and FP64 for F64. */
+typedef enum { DW_PREC_F64 = 0, DW_PREC_F32 = 1, DW_PREC_F16 = 2, DW_PREC_BF16 = 3 } dw_prec;
+
+/* Device-memory allocator. alloc returns a device pointer of at least
+ * `bytes` bytes usable on `stream` (NULL on failure); release frees it. If
+ * the context is created with a NULL allocator, hipMalloc/hipFree are used. */
+typedef struct dw_allocator {
+  void* (*alloc)(size_t bytes, hipStream_t stream, void* user);
+  void (*release)(void* ptr, hipStream_t stream, void* user);
+  void* user;
+} dw_allocator;
+
+typedef struct dw_ctx_s* dw_ctx;
+typedef struct dw_field_s* dw_field;
+typedef struct dw_server_s* dw_server;
+
+/* SAP preconditioner parameters (Alg. 2; Sections 3 and 5).
+ *   block[4]  domain extents; they must divide L and give an even number of
+ *             domains per direction (Section 2, red/black colouring); they
+ *             must equal the block extents the field was created with.
+ *   ncycles   SAP cycles s per application (one cycle = both colours).
+ *   nmr       minimal-residual steps per block solve, from y = 0.
+ *   storage   dw_prec of the preconditioner's fields. */
+typedef struct sap_params {
+  int32_t block[4];
+  int32_t ncycles;
+  int32_t nmr;
+  int32_t storage;
+  int32_t reserved;
+} sap_params;
+
+/* FGMRES-DR parameters (Alg. 4; Section 4.7).
+ *   m          total basis size per cycle, including the k deflation vectors
+ *              (cycles after the first perform m - k Arnoldi steps), 1..48.
+ *   k          deflation space dimension, 0 <= k < m (0 = FGMRES(m)).
+ *   max_iter   iteration limit; one iteration = one flexible Arnoldi step.
+ *   tol        stop when ||b - D x||_2 <= tol ||b||_2 (explicit FP64 residual).
+ *   restart_t  clean restart (no deflation) when ||r_explicit|| / ||r_implicit||
+ *              exceeds this threshold (the paper suggests 2..10).
+ *   sap        preconditioner parameters.
+ *   shared_defl  multi-RHS only: 1 = project every RHS's restart residual
+ *              onto the deflation space of RHS 0 (see fgmresdr_solve).
+ *   flags      reserved, pass 0. */
+typedef struct fgmresdr_params {
+  int32_t m;
+  int32_t k;
+  int32_t max_iter;
+  int32_t shared_defl;
+  double tol;
+  double restart_t;
+  sap_params sap;
+  int32_t flags;
+  int32_t reserved;
+} fgmresdr_params;
+
+/* Per-RHS solver statistics. */
+typedef struct dw_solve_stats {
+  int32_t converged;       /* 1 if ||b - D x|| <= tol ||b|| */
+  int32_t iterations;      /* flexible Arnoldi steps */
+  int32_t cycles;          /* restart cycles */
+  int32_t clean_restarts;  /* restarts without deflation (Section 4.7) */
+  double true_relres;      /* ||b - D x|| / ||b|| in FP64 at exit */
+  double implicit_relres;  /* least-squares residual of the last cycle / ||b|| */
+  double seconds;          /* wall-clock time of the solve */
+} dw_solve_stats;
+
+/* Thread-local text of the last error (never NULL). */
+const char* dw_last_error(void);
+
+/* Creates a context on HIP device `device`. `alloc` may be NULL (hipMalloc).
+ * The allocator struct is copied. */
+dw_status dw_ctx_create(int32_t device, const dw_allocator* alloc, dw_ctx* out);
+dw_status dw_ctx_destroy(dw_ctx ctx);
+
+/* Imports a gauge field (Section 2: U_mu(n) in SU(3), one per site and
+ * direction) for lattice L, tiled into SAP domains of extents `block`.
+ * U_dev: canonical complex128 gauge array on the device (read during the
+ * call's stream work only; the library keeps its own FP64, FP32, FP16 and
+ * BF16 copies in a private block-tiled layout). DW_EINVAL if the blocks do
+ * not tile L with an even count per direction or exceed 1024 sites. */
+dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4], const double* U_dev,
+                          hipStream_t stream, dw_field* out);
+dw_status dw_field_destroy(dw_field field);
+/* Lattice sites of the field (convenience for callers sizing buffers). */
+int64_t dw_field_volume(dw_field field);
+
+/* y = D x for nrhs right-hand sides, FP64 (eq. 1). x and y: canonical
+ * spinor arrays of nrhs * V * 12 complex128 each; they must not overlap. */
+dw_status dw_apply(dw_field field, double m0, const double* x, double* y, int32_t nrhs, hipStream_t stream);
+
+/* Benchmark path: y = D x on buffers already in the library's internal
+ * block-tiled layout at storage precision `prec` (complex pairs of that
+ * precision, nrhs * V * 12 pairs each; size from dw_internal_bytes). The
+ * hopping term uses the field's links at the same precision and FP32
+ * arithmetic (FP64 for DW_PREC_F64). dw_pack / dw_unpack convert between
+ * the canonical FP64 layout and this one. */
+dw_status dw_apply_ex(dw_field field, double m0, int32_t prec, const void* x_int, void* y_int, int32_t nrhs,
+                      hipStream_t stream);
+size_t dw_internal_bytes(dw_field field, int32_t prec, int32_t nrhs);
+dw_status dw_pack(dw_field field, int32_t prec, const double* x, void* x_int, int32_t nrhs, hipStream_t stream);
+dw_status dw_unpack(dw_field field, int32_t prec, const void* x_int, double* x, int32_t nrhs, hipStream_t stream);
+
+/* z = M v: `sap.ncycles` SAP cycles (Alg. 2) from z = 0, each block system
+ * D^l y^l = r^l (eq. 2) solved by `sap.nmr` minimal-residual steps in the
+ * storage precision `sap.storage`. Blocks of colour 0 (even sum of block
+ * coordinates, containing the origin) go first; the correction is added,
+ * z^l += y^l. v and z: canonical spinor arrays (nrhs each), no overlap. */
+dw_status sap_precondition(dw_field field, double m0, const sap_params* sap, const double* v, double* z,
+                           int32_t nrhs, hipStream_t stream);
+
+/* Solves D x = b by SAP-preconditioned FGMRES-DR(m, k) (Alg. 4) from x = 0
+ * for nrhs right-hand sides (solved in lock-step, every SAP and stencil
+ * launch covering all of them). Arnoldi, Hessenberg updates, harmonic Ritz
+ * deflation and the least-squares problems are FP64; the explicit residual
+ * is computed in FP64 once per cycle and enters the least-squares right-hand
+ * side (Section 4.7); the preconditioner runs at `params->sap.storage`.
+ * b, x: canonical spinor arrays (nrhs each). stats: host array of nrhs
+ * entries (may be NULL). Synchronises `stream` once per cycle and before
+ * returning. Returns DW_ENOTCONV if any RHS stopped at max_iter (x then
+ * holds its last iterate and stats are filled). */
+dw_status fgmresdr_solve(dw_field field, double m0, const fgmresdr_params* params, const double* b, double* x,
+                         int32_t nrhs, dw_solve_stats* stats, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWSAP_H */

@@ -1,0 +1,318 @@
+"""Python binding of libdwsap, the MI355X SAP-preconditioned FGMRES-DR solver
+for the Wilson-Dirac operator (arXiv:1204.5463).
+
+This module only marshals arguments: it loads the HIP library, passes
+device pointers of PyTorch tensors and the current HIP stream, and turns
+status codes into exceptions. Every step of the method runs in the
+library's kernels. PyTorch supplies device memory (through its caching
+allocator, handed to the library as an allocator callback) and streams.
+
+Field layout at this boundary: complex128 tensors on the GPU,
+  spinor  psi[(rhs,) t, z, y, x, spin, colour]
+  gauge   U[mu, t, z, y, x, a, b]          (mu = x, y, z, t)
+with lattice extents L = (Lx, Ly, Lz, Lt).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+__all__ = [
+    "DW_PREC_F64", "DW_PREC_F32", "DW_PREC_F16", "DW_PREC_BF16", "PREC_NAMES",
+    "DwError", "NotConverged", "Context", "Field", "SapParams", "SolverParams", "SolveStats",
+    "lib", "load",
+]
+
+DW_OK, DW_EINVAL, DW_ENOMEM, DW_EHIP, DW_ENOTCONV, DW_EBUSY, DW_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+DW_PREC_F64, DW_PREC_F32, DW_PREC_F16, DW_PREC_BF16 = 0, 1, 2, 3
+PREC_NAMES = {"f64": DW_PREC_F64, "f32": DW_PREC_F32, "f16": DW_PREC_F16, "bf16": DW_PREC_BF16}
+PAIR_BYTES = {DW_PREC_F64: 16, DW_PREC_F32: 8, DW_PREC_F16: 4, DW_PREC_BF16: 4}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdwsap.so")
+
+
+class DwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dwsap status {status}: {msg}")
+        self.status = status
+
+
+class NotConverged(DwError):
+    pass
+
+
+class _SapParams(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32 * 4), ("ncycles", ctypes.c_int32), ("nmr", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _SolverParams(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("k", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("shared_defl", ctypes.c_int32), ("tol", ctypes.c_double), ("restart_t", ctypes.c_double),
+                ("sap", _SapParams), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("clean_restarts", ctypes.c_int32), ("true_relres", ctypes.c_double),
+                ("implicit_relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+@dataclasses.dataclass
+class SapParams:
+    """SAP preconditioner (Alg. 2): block extents, cycles s, MR steps, storage precision."""
+    block: tuple = (4, 4, 4, 4)
+    ncycles: int = 1
+    nmr: int = 4
+    storage: int = DW_PREC_F64
+
+    def _c(self):
+        p = _SapParams()
+        for i in range(4):
+            p.block[i] = int(self.block[i])
+        p.ncycles, p.nmr, p.storage, p.reserved = int(self.ncycles), int(self.nmr), int(self.storage), 0
+        return p
+
+
+@dataclasses.dataclass
+class SolverParams:
+    """FGMRES-DR(m, k) (Alg. 4) with the Section 4.7 clean-restart threshold."""
+    m: int = 20
+    k: int = 5
+    max_iter: int = 10000
+    tol: float = 1e-10
+    restart_t: float = 5.0
+    sap: SapParams = dataclasses.field(default_factory=SapParams)
+    shared_defl: int = 0
+
+    def _c(self):
+        p = _SolverParams()
+        p.m, p.k, p.max_iter, p.shared_defl = int(self.m), int(self.k), int(self.max_iter), int(self.shared_defl)
+        p.tol, p.restart_t = float(self.tol), float(self.restart_t)
+        p.sap = self.sap._c()
+        p.flags = p.reserved = 0
+        return p
+
+
+@dataclasses.dataclass
+class SolveStats:
+    converged: bool
+    iterations: int
+    cycles: int
+    clean_restarts: int
+    true_relres: float
+    implicit_relres: float
+    seconds: float
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdwsap.so. Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libdwsap.so not found at {path}; build it with `python -m paper_1204_5463_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32
+    sig = {
+        "dw_last_error": (ctypes.c_char_p, []),
+        "dw_ctx_create": (st, [i32, ctypes.POINTER(_Allocator), ctypes.POINTER(vp)]),
+        "dw_ctx_destroy": (st, [vp]),
+        "dw_field_create": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, ctypes.POINTER(vp)]),
+        "dw_field_destroy": (st, [vp]),
+        "dw_field_volume": (i64, [vp]),
+        "dw_apply": (st, [vp, dbl, vp, vp, i32, vp]),
+        "dw_apply_ex": (st, [vp, dbl, i32, vp, vp, i32, vp]),
+        "dw_internal_bytes": (ctypes.c_size_t, [vp, i32, i32]),
+        "dw_pack": (st, [vp, i32, vp, vp, i32, vp]),
+        "dw_unpack": (st, [vp, i32, vp, vp, i32, vp]),
+        "sap_precondition": (st, [vp, dbl, ctypes.POINTER(_SapParams), vp, vp, i32, vp]),
+        "fgmresdr_solve": (st, [vp, dbl, ctypes.POINTER(_SolverParams), vp, vp, i32, ctypes.POINTER(_Stats), vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def lib():
+    return load()
+
+
+def _check(status, what=""):
+    if status != DW_OK:
+        msg = lib().dw_last_error().decode(errors="replace")
+        if status == DW_ENOTCONV:
+            raise NotConverged(status, msg)
+        raise DwError(status, f"{what}: {msg}" if what else msg)
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev_ptr(t: torch.Tensor, dtype=torch.complex128):
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context on one device, allocating through PyTorch's caching allocator."""
+
+    def __init__(self, device: int = 0, use_torch_allocator: bool = True):
+        L = lib()
+        self.device = device
+        self._alloc = None
+        if use_torch_allocator:
+            dev = device
+
+            def _a(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+                except Exception:
+                    return None
+
+            def _f(ptr, stream, user):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._afn, self._ffn = _ALLOC_FN(_a), _FREE_FN(_f)
+            self._alloc = _Allocator(self._afn, self._ffn, None)
+        h = ctypes.c_void_p()
+        _check(L.dw_ctx_create(device, ctypes.byref(self._alloc) if self._alloc else None, ctypes.byref(h)),
+               "dw_ctx_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Field:
+    """A gauge field tiled into SAP blocks (the library keeps its own copies)."""
+
+    def __init__(self, ctx: Context, L, block, U: torch.Tensor, stream=None):
+        self.ctx = ctx
+        self.L = tuple(int(v) for v in L)
+        self.block = tuple(int(v) for v in block)
+        Lx, Ly, Lz, Lt = self.L
+        if tuple(U.shape) != (4, Lt, Lz, Ly, Lx, 3, 3):
+            raise ValueError(f"gauge shape {tuple(U.shape)} does not match L={self.L}")
+        La = (ctypes.c_int32 * 4)(*self.L)
+        Ba = (ctypes.c_int32 * 4)(*self.block)
+        h = ctypes.c_void_p()
+        _check(lib().dw_field_create(ctx.handle, La, Ba, _dev_ptr(U), _stream(stream), ctypes.byref(h)),
+               "dw_field_create")
+        self.handle = h
+        self.volume = int(lib().dw_field_volume(h))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dw_field_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --------------------------------------------------------------
+    def _nrhs(self, t):
+        n = t.numel() // (self.volume * 12)
+        if n * self.volume * 12 != t.numel():
+            raise ValueError("spinor tensor size is not a multiple of the lattice volume * 12")
+        return n
+
+    def apply(self, m0: float, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+        """y = D x (eq. 1), FP64. Synchronous."""
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().dw_apply(self.handle, float(m0), _dev_ptr(x), _dev_ptr(y), self._nrhs(x), _stream(stream)),
+               "dw_apply")
+        return y
+
+    def internal_bytes(self, prec, nrhs=1):
+        return int(lib().dw_internal_bytes(self.handle, int(prec), int(nrhs)))
+
+    def pack(self, prec, x: torch.Tensor, stream=None):
+        nrhs = self._nrhs(x)
+        out = torch.empty(self.internal_bytes(prec, nrhs), dtype=torch.uint8, device=x.device)
+        _check(lib().dw_pack(self.handle, int(prec), _dev_ptr(x), _dev_ptr(out, None), nrhs, _stream(stream)),
+               "dw_pack")
+        return out
+
+    def unpack(self, prec, xi: torch.Tensor, nrhs=1, stream=None):
+        shp = (nrhs,) + tuple(reversed(self.L)) + (4, 3)
+        out = torch.empty(shp, dtype=torch.complex128, device=xi.device)
+        _check(lib().dw_unpack(self.handle, int(prec), _dev_ptr(xi, None), _dev_ptr(out), nrhs, _stream(stream)),
+               "dw_unpack")
+        return out
+
+    def apply_ex(self, m0, prec, xi: torch.Tensor, yi: torch.Tensor, nrhs=1, stream=None):
+        """y = D x on internal-layout buffers at precision prec (asynchronous)."""
+        _check(lib().dw_apply_ex(self.handle, float(m0), int(prec), _dev_ptr(xi, None), _dev_ptr(yi, None),
+                                 int(nrhs), _stream(stream)), "dw_apply_ex")
+
+    def sap(self, m0: float, params: SapParams, v: torch.Tensor, z: torch.Tensor | None = None, stream=None):
+        """z = M v: SAP (Alg. 2) with MR block solves. Synchronous."""
+        if z is None:
+            z = torch.empty_like(v)
+        p = params._c()
+        _check(lib().sap_precondition(self.handle, float(m0), ctypes.byref(p), _dev_ptr(v), _dev_ptr(z),
+                                      self._nrhs(v), _stream(stream)), "sap_precondition")
+        return z
+
+    def solve(self, m0: float, params: SolverParams, b: torch.Tensor, x: torch.Tensor | None = None,
+              stream=None, raise_on_notconv=True):
+        """x = D^{-1} b by SAP-preconditioned FGMRES-DR (Alg. 4). Returns (x, [SolveStats])."""
+        if x is None:
+            x = torch.empty_like(b)
+        nrhs = self._nrhs(b)
+        st = (_Stats * nrhs)()
+        p = params._c()
+        status = lib().fgmresdr_solve(self.handle, float(m0), ctypes.byref(p), _dev_ptr(b), _dev_ptr(x), nrhs, st,
+                                      _stream(stream))
+        stats = [SolveStats(bool(s.converged), s.iterations, s.cycles, s.clean_restarts, s.true_relres,
+                            s.implicit_relres, s.seconds) for s in st]
+        if status == DW_ENOTCONV and not raise_on_notconv:
+            return x, stats
+        _check(status, "fgmresdr_solve")
+        return x, stats
+
+
+def to_device(a, device="cuda"):
+    """numpy complex array -> contiguous complex128 tensor on the GPU."""
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)

@@ -1,0 +1,119 @@
+// Internal runtime structures and kernel launcher declarations.
+#pragma once
+
+#include <stdarg.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/dwsap.h"
+#include "dw_geom.hpp"
+
+struct dw_ctx_s {
+  int device;
+  dw_allocator alloc;
+  bool user_alloc;
+};
+
+struct dw_field_s {
+  dw_ctx ctx;
+  dw::Geom g;
+  void* U[4];  // links per dw_prec, internal layout
+};
+
+namespace dw {
+
+// ---- errors -----------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define DW_CHECK_HIP(expr)                                                                    \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      ::dw::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return DW_EHIP;                                                                         \
+    }                                                                                         \
+  } while (0)
+
+#define DW_CHECK_LAUNCH()                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = hipGetLastError();                                                        \
+    if (e_ != hipSuccess) {                                                                   \
+      ::dw::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
+      return DW_EHIP;                                                                         \
+    }                                                                                         \
+  } while (0)
+
+#define DW_TRY(expr)              \
+  do {                            \
+    dw_status s_ = (expr);        \
+    if (s_ != DW_OK) return s_;   \
+  } while (0)
+
+// ---- device memory ------------------------------------------------------------
+void* dev_alloc(dw_ctx ctx, size_t bytes, hipStream_t stream);
+void dev_free(dw_ctx ctx, void* p, hipStream_t stream);
+
+// Scoped device buffer from the context allocator.
+struct DevBuf {
+  dw_ctx ctx = nullptr;
+  hipStream_t stream = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  dw_status alloc(dw_ctx c, size_t n, hipStream_t s) {
+    reset();
+    ctx = c;
+    stream = s;
+    bytes = n;
+    p = n ? dev_alloc(c, n, s) : nullptr;
+    if (n && !p) {
+      set_error("device allocation of %zu bytes failed", n);
+      return DW_ENOMEM;
+    }
+    return DW_OK;
+  }
+  void reset() {
+    if (p) dev_free(ctx, p, stream);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// bytes of one complex pair per precision
+inline size_t pair_bytes(int prec) { return prec == DW_PREC_F64 ? 16 : prec == DW_PREC_F32 ? 8 : 4; }
+
+// ---- launchers (kernels in the .hip files) --------------------------------------
+// All counts in complex pairs; nrhs fields are stacked with stride V*12 pairs.
+dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* out, double scale, int nrhs,
+                             hipStream_t s);
+dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* out, double scale, int nrhs,
+                               hipStream_t s);
+dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out, hipStream_t s);
+// elementwise out = scale * in over n pairs (precision conversion)
+dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s);
+
+// y = scale * D x (mode 0) or y = b - scale * D x (mode 1), internal layout.
+// prec_x: DW_PREC_F64 or DW_PREC_F32 input with FP64 links/output/arithmetic
+// when outer = true; otherwise everything at precision prec_x (FP32 math).
+dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
+                              double* y, const double* b, int mode, int nrhs, long long x_rhs_stride,
+                              long long y_rhs_stride, hipStream_t s);
+dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
+                             hipStream_t s);
+
+// One SAP colour sweep: for every block of `colour`, r = v - D z on the
+// block, nmr MR steps on D^l y = r, z += y. v at storage precision `prec`,
+// z at FP64 (prec F64) or FP32 (otherwise). z_zero: z is zero on entry.
+dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
+                            int nmr, int z_zero, int nrhs, long long v_rhs_stride, long long z_rhs_stride,
+                            hipStream_t s);
+
+}  // namespace dw

@@ -1,0 +1,60 @@
+// Launchers of the Krylov-space kernels (long vectors and small dense
+// FP64 problems). All pointers are device pointers; complex numbers are
+// (re, im) double pairs. Small matrices are column-major with leading
+// dimension kLd (row i, column j at i + j*kLd).
+#pragma once
+
+#include "dw_internal.hpp"
+
+namespace dw {
+
+constexpr int kBlasGrid = 1024;  // workgroups of the multi-dot kernels (partials per column)
+constexpr int kMaxM = 48;        // largest restart length m
+constexpr int kLd = kMaxM + 1;   // leading dimension of small matrices
+
+// out[c*ostride] (= or += per op) <- V_c^H w for c < ncols; partials holds
+// ncols * kBlasGrid pairs of scratch
+dw_status blas_dots(int prec_v, const void* V, long long stride, int ncols, const double* w, long long n,
+                    double* partials, double* out, int ostride, int op, hipStream_t s);
+// w -= sum_c h_c V_c
+dw_status blas_sub_cols(const double* V, long long stride, int ncols, const double* h, double* w, long long n,
+                        hipStream_t s);
+// y = alpha[0] * x (alpha a device double)
+dw_status blas_scale(const double* x, double* y, const double* alpha, long long n, hipStream_t s);
+// x += scale * sum_c coef_c Z_c
+dw_status blas_combine(int prec_z, const void* Z, long long stride, int ncols, const double* coef, double scale,
+                       double* x, long long n, hipStream_t s);
+// in place V[:, 0:nout] = V[:, 0:nin] Q, Q column-major with leading dimension ldq
+dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const double* Q, int ldq, int nout, long long n,
+                      hipStream_t s);
+
+// ---- small dense FP64 (one workgroup) ---------------------------------------------
+// Scalars block written by dense_step / dense_cycle_end (doubles):
+enum {
+  kSclHnext = 0,      // h_{j+1,j}
+  kSclHinv = 1,       // 1 / h_{j+1,j} (0 on breakdown)
+  kSclResImp = 2,     // implicit residual norm ||c - H eta|| of the current step
+  kSclBreak = 3,      // 1.0 if the step broke down
+  kSclStatus = 4,     // deflation status (0 ok, 1 singular H_m, 2 eigen failure, 3 non-finite)
+  kSclBeta = 5,       // norm used for a fresh start
+  kSclBetaInv = 6,
+  kSclCount = 8
+};
+
+// Completes Arnoldi step j: H(0:j, j) = h1 + h2, H(j+1, j) = sqrt(nrm2.re),
+// breakdown test, implicit residual of the (j+2) x (j+1) least-squares
+// problem with right-hand side c.
+dw_status dense_step(double* H, int j, const double* h1, const double* h2, const double* nrm2, const double* c,
+                     double* scal, double bd_tol, hipStream_t s);
+// eta = argmin ||c(0:cols+1) - H(0:cols+1, 0:cols) eta||; scal[kSclResImp] = residual
+dw_status dense_lsq(const double* H, int cols, const double* c, double* eta, double* scal, hipStream_t s);
+// Deflated restart of a cycle with mm columns (Lemma 1, Alg. 4):
+// harmonic Ritz pairs, G_{k+1} = [[G_k; 0], c - H eta], QR -> Q ((mm+1) x (k+1), ld kLd),
+// H <- [Q^H H Q_k in rows 0..k, cols 0..k-1; 0 elsewhere]; ritz <- all mm
+// harmonic Ritz values sorted by modulus; scal[kSclStatus] = status.
+dw_status dense_deflate(double* H, int mm, int k, const double* c, const double* eta, double* Q, double* ritz,
+                        double* scal, hipStream_t s);
+// fresh start: scal[kSclBeta] = sqrt(nrm2.re), scal[kSclBetaInv] = 1/beta, c = beta e_1, H = 0
+dw_status dense_fresh(double* H, double* c, const double* nrm2, double* scal, hipStream_t s);
+
+}  // namespace dw

@@ -1,0 +1,154 @@
+// The Wilson-Dirac hopping term, site by site (paper Section 2, eq. 1).
+//
+//   (D x)(n) = (4 + m0) x(n)
+//              - 1/2 sum_mu [ (1 - g_mu) U_mu(n) x(n+mu) + (1 + g_mu) U_mu(n-mu)^+ x(n-mu) ]
+//
+// Each of the 8 hops projects the neighbour spinor onto a half spinor
+// (two spin components), multiplies both by the SU(3) link and rebuilds
+// the lower two spin components from the upper two. The gamma matrices
+// are in the Euclidean chiral basis
+//   g_k = [[0, -i s_k], [i s_k, 0]] (k = x, y, z),  g_t = [[0, 1], [1, 0]],
+// for which (1 -/+ g_mu) psi = [h; c h] with h = psi_up -/+ A_mu psi_dn.
+//
+// Per direction and sign the projection is h0 = psi0 + a*psi_pa,
+// h1 = psi1 + b*psi_pb and the reconstruction r2 = c*h_qc, r3 = d*h_qd,
+// with a, b, c, d in {+1, -1, +i, -i}.
+#pragma once
+
+#include <type_traits>
+
+#include "dw_geom.hpp"
+#include "dw_types.hpp"
+
+namespace dw {
+
+enum { CP1 = 0, CM1 = 1, CPI = 2, CMI = 3 };
+
+template <int K, typename T>
+__device__ __forceinline__ cplx<T> coef(cplx<T> z) {
+  if constexpr (K == CP1) return z;
+  else if constexpr (K == CM1) return -z;
+  else if constexpr (K == CPI) return mul_i(z);
+  else return mul_mi(z);
+}
+
+// flip the sign of a coefficient (backward hops use 1 + g instead of 1 - g)
+constexpr int neg(int k) { return k == CP1 ? CM1 : k == CM1 ? CP1 : k == CPI ? CMI : CPI; }
+
+template <int MU>
+struct proj_table;
+// forward hop (1 - g_mu)
+template <> struct proj_table<0> { static constexpr int pa = 3, a = CPI, pb = 2, b = CPI, qc = 1, c = CMI, qd = 0, d = CMI; };
+template <> struct proj_table<1> { static constexpr int pa = 3, a = CP1, pb = 2, b = CM1, qc = 1, c = CM1, qd = 0, d = CP1; };
+template <> struct proj_table<2> { static constexpr int pa = 2, a = CPI, pb = 3, b = CMI, qc = 0, c = CMI, qd = 1, d = CPI; };
+template <> struct proj_table<3> { static constexpr int pa = 2, a = CM1, pb = 3, b = CM1, qc = 0, c = CM1, qd = 1, d = CM1; };
+
+// acc += (1 -/+ g_mu) W psi, where W = U (DIR > 0) or U^+ (DIR < 0).
+// psi(comp) returns the neighbour spinor component comp = spin*3 + colour,
+// u(e) returns link entry e = a*3 + b.
+template <int MU, int DIR, typename T, typename PsiF, typename UF>
+__device__ __forceinline__ void hop(cplx<T> acc[12], PsiF&& psi, UF&& u) {
+  using P = proj_table<MU>;
+  constexpr int A = DIR > 0 ? P::a : neg(P::a);
+  constexpr int B = DIR > 0 ? P::b : neg(P::b);
+  constexpr int C = DIR > 0 ? P::c : neg(P::c);
+  constexpr int D = DIR > 0 ? P::d : neg(P::d);
+  cplx<T> h0[3], h1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h0[a] = psi(a) + coef<A>(psi(P::pa * 3 + a));
+    h1[a] = psi(3 + a) + coef<B>(psi(P::pb * 3 + a));
+  }
+  cplx<T> w[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) w[e] = u(e);
+  cplx<T> g0[3], g1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if constexpr (DIR > 0) {
+        s0 += w[a * 3 + b] * h0[b];
+        s1 += w[a * 3 + b] * h1[b];
+      } else {
+        s0 += cdot(w[b * 3 + a], h0[b]);
+        s1 += cdot(w[b * 3 + a], h1[b]);
+      }
+    }
+    g0[a] = s0;
+    g1[a] = s1;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] += g0[a];
+    acc[3 + a] += g1[a];
+    acc[6 + a] += coef<C>(P::qc == 0 ? g0[a] : g1[a]);
+    acc[9 + a] += coef<D>(P::qd == 0 ? g0[a] : g1[a]);
+  }
+}
+
+// Dispatch hop h = 2*mu + (0: forward, 1: backward). h is uniform across the
+// wave, so the switch is a scalar branch to code with compile-time
+// projection coefficients.
+template <typename T, typename PsiF, typename UF>
+__device__ __forceinline__ void hop_dispatch(int h, cplx<T> acc[12], PsiF&& psi, UF&& u) {
+  switch (h) {
+    case 0: hop<0, +1, T>(acc, psi, u); break;
+    case 1: hop<0, -1, T>(acc, psi, u); break;
+    case 2: hop<1, +1, T>(acc, psi, u); break;
+    case 3: hop<1, -1, T>(acc, psi, u); break;
+    case 4: hop<2, +1, T>(acc, psi, u); break;
+    case 5: hop<2, -1, T>(acc, psi, u); break;
+    case 6: hop<3, +1, T>(acc, psi, u); break;
+    default: hop<3, -1, T>(acc, psi, u); break;
+  }
+}
+
+// Hopping sum over all 8 neighbours on the periodic lattice, reading the
+// spinor through xin(block, local, comp) and links from U (internal layout).
+// The hop loop is deliberately not unrolled: unrolling lets the compiler
+// hoist all 8 hops' loads and spill; one hop's loads in flight per wave
+// plus other resident waves hide the latency.
+template <typename T, typename SG, typename XF>
+__device__ __forceinline__ void hop_sum_lattice(const Geom& g, int b, int l, const int bc[4], const int lc[4],
+                                                const SG* __restrict__ U, XF&& xin, cplx<T> acc[12]) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll 1
+  for (int h = 0; h < 8; ++h) {
+    const int mu = h >> 1;
+    int nb, nl;
+    long long ub;
+    if ((h & 1) == 0) {
+      neighbour<+1>(g, b, l, bc, lc, mu, &nb, &nl);
+      ub = gauge_index(g, b, mu, 0, l);
+    } else {
+      neighbour<-1>(g, b, l, bc, lc, mu, &nb, &nl);
+      ub = gauge_index(g, nb, mu, 0, nl);
+    }
+    hop_dispatch<T>(h, acc, [&](int comp) { return xin(nb, nl, comp); },
+                    [&](int e) { return ld<T>(U + ub + (long long)e * g.bvol); });
+  }
+}
+
+// Hopping sum restricted to one block (eq. 2): hops that leave the block
+// are dropped. The block's spinor is read through xin(local, comp).
+template <typename T, typename SG, typename XF>
+__device__ __forceinline__ void hop_sum_block(const Geom& g, int b, int l, const int lc[4], const SG* __restrict__ U,
+                                              XF&& xin, cplx<T> acc[12]) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll 1
+  for (int h = 0; h < 8; ++h) {
+    const int mu = h >> 1;
+    const bool fwd = (h & 1) == 0;
+    if (fwd ? lc[mu] >= g.B[mu] - 1 : lc[mu] <= 0) continue;
+    const int nl = fwd ? l + g.lstride[mu] : l - g.lstride[mu];
+    const long long ub = gauge_index(g, b, mu, 0, fwd ? l : nl);
+    hop_dispatch<T>(h, acc, [&](int comp) { return xin(nl, comp); },
+                    [&](int e) { return ld<T>(U + ub + (long long)e * g.bvol); });
+  }
+}
+
+}  // namespace dw

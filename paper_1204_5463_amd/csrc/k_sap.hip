@@ -1,0 +1,170 @@
+// One colour of the Schwarz alternating procedure (paper Section 2, Alg. 2).
+//
+// One workgroup per block of the given colour; blocks of one colour do not
+// couple (red/black colouring with an even block count per direction), so
+// the whole colour is one launch. Per block:
+//   1. block residual r = (v - D z) restricted to the block, using z on the
+//      block and its one-site halo in blocks of the other colour;
+//   2. nmr minimal-residual steps on D^l y = r (eq. 2) starting from y = 0,
+//      alpha = (p^H rho) / (p^H p) over the block's sites, with the
+//      residual rho kept in LDS so that neighbours can read it;
+//   3. z += y on the block.
+// Same-colour blocks never read each other's z, so updating z in place is
+// race-free. Arithmetic is T (float for FP32/FP16/BF16 storage, double for
+// FP64 storage); the block inner products are wavefront reductions followed
+// by a fixed-order sum over the workgroup's waves (deterministic).
+#include "dw_internal.hpp"
+#include "dw_stencil.hpp"
+
+namespace dw {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T a) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+  return a;
+}
+
+template <typename T, typename SV, typename SZ, typename SG, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+    k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
+                 int nmr, int z_zero, long long vs, long long zs) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem);
+  const int nw = blockDim.x / kWave;
+  T* red = reinterpret_cast<T*>(rho_s + 12 * g.bvol);  // 2 buffers x nw x 3
+  const int l = threadIdx.x;
+  const bool active = l < g.bvol;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int b = colour * g.nbc + blockIdx.x;
+  const SV* vr = v + (long long)blockIdx.y * vs;
+  SZ* zr = z + (long long)blockIdx.y * zs;
+  const T half = (T)0.5;
+
+  int bc[4], lc[4] = {0, 0, 0, 0};
+  decode_block(g, b, bc);
+  cplx<T> rho[12], y[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    rho[c] = mk<T>(0, 0);
+    y[c] = mk<T>(0, 0);
+  }
+  if (active) {
+    decode_local(g, l, lc);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c] = ld<T>(vr + spinor_index(g, b, c, l));
+    if (!z_zero) {
+      cplx<T> acc[12];
+      hop_sum_lattice<T>(g, b, l, bc, lc, U,
+                         [&](int nb, int nl, int comp) { return ld<T>(zr + spinor_index(g, nb, comp, nl)); }, acc);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rho[c] = rho[c] - diag * ld<T>(zr + spinor_index(g, b, c, l)) + half * acc[c];
+    }
+  }
+
+  for (int it = 0; it < nmr; ++it) {
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rho_s[c * g.bvol + l] = rho[c];
+    }
+    __syncthreads();
+    cplx<T> p[12];
+    T nre = 0, nim = 0, den = 0;
+    if (active) {
+      hop_sum_block<T>(g, b, l, lc, U, [&](int nl, int comp) { return rho_s[comp * g.bvol + nl]; }, p);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        p[c] = diag * rho[c] - half * p[c];
+        cplx<T> d = cdot(p[c], rho[c]);
+        nre += d.re;
+        nim += d.im;
+        den += norm2(p[c]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) p[c] = mk<T>(0, 0);
+    }
+    nre = wave_sum(nre);
+    nim = wave_sum(nim);
+    den = wave_sum(den);
+    T* rb = red + (it & 1) * 3 * nw;
+    if (lane == 0) {
+      rb[wave * 3 + 0] = nre;
+      rb[wave * 3 + 1] = nim;
+      rb[wave * 3 + 2] = den;
+    }
+    __syncthreads();
+    nre = nim = den = 0;
+    for (int w = 0; w < nw; ++w) {
+      nre += rb[w * 3 + 0];
+      nim += rb[w * 3 + 1];
+      den += rb[w * 3 + 2];
+    }
+    cplx<T> alpha = den > (T)0 ? mk<T>(nre / den, nim / den) : mk<T>(0, 0);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      y[c] += alpha * rho[c];
+      rho[c] -= alpha * p[c];
+    }
+  }
+  __syncthreads();  // every thread has read z on this block before it is updated
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const long long idx = spinor_index(g, b, c, l);
+      st(zr + idx, z_zero ? y[c] : ld<T>(zr + idx) + y[c]);
+    }
+  }
+}
+
+template <typename T, typename SV, typename SZ, typename SG, int MAXT>
+dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
+                 int nrhs, long long vs, long long zs, hipStream_t s) {
+  const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
+  const size_t shmem = (size_t)12 * g.bvol * sizeof(cplx<T>) + (size_t)2 * 3 * (threads / kWave) * sizeof(T);
+  if (shmem > 160 * 1024) {
+    set_error("SAP block of %d sites needs %zu bytes of LDS", g.bvol, shmem);
+    return DW_EINVAL;
+  }
+  if (shmem > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) {
+      set_error("hipFuncSetAttribute(LDS %zu bytes) failed: %s", shmem, hipGetErrorString(e));
+      return DW_EHIP;
+    }
+  }
+  dim3 grid((unsigned)g.nbc, (unsigned)nrhs);
+  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
+                     (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs);
+  DW_CHECK_LAUNCH();
+  return DW_OK;
+}
+
+template <typename T, typename SV, typename SZ, typename SG>
+dw_status launch(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
+                 int nrhs, long long vs, long long zs, hipStream_t s) {
+  if (g.bvol <= 256) return launch_t<T, SV, SZ, SG, 256>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+  if (g.bvol <= 512) return launch_t<T, SV, SZ, SG, 512>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+  return launch_t<T, SV, SZ, SG, 1024>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+}
+
+}  // namespace
+
+dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
+                            int nmr, int z_zero, int nrhs, long long vs, long long zs, hipStream_t s) {
+  switch (prec) {
+    case DW_PREC_F64: return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+    case DW_PREC_F32: return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+    case DW_PREC_F16: return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+    case DW_PREC_BF16: return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+    default: set_error("unknown precision %d", prec); return DW_EINVAL;
+  }
+}
+
+}  // namespace dw

@@ -1,0 +1,300 @@
+// Context, field and operator entry points of the C ABI.
+#include <stdio.h>
+#include <string.h>
+
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <string>
+
+#include "dw_internal.hpp"
+#include "dw_kernels.hpp"
+#include <math.h>
+
+namespace dw {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+void* dev_alloc(dw_ctx ctx, size_t bytes, hipStream_t stream) {
+  if (ctx->user_alloc) return ctx->alloc.alloc(bytes, stream, ctx->alloc.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(dw_ctx ctx, void* p, hipStream_t stream) {
+  if (!p) return;
+  if (ctx->user_alloc) {
+    ctx->alloc.release(p, stream, ctx->alloc.user);
+    return;
+  }
+  // hipFree synchronises the device; callers free only at the end of a call
+  (void)hipFree(p);
+}
+
+}  // namespace dw
+
+using namespace dw;
+
+namespace {
+
+dw_status check_device(dw_ctx ctx) {
+  int cur = -1;
+  DW_CHECK_HIP(hipGetDevice(&cur));
+  if (cur != ctx->device) DW_CHECK_HIP(hipSetDevice(ctx->device));
+  return DW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dw_last_error(void) { return dw::g_last_error.c_str(); }
+
+dw_status dw_ctx_create(int32_t device, const dw_allocator* alloc, dw_ctx* out) {
+  clear_error();
+  if (!out) {
+    set_error("dw_ctx_create: null output pointer");
+    return DW_EINVAL;
+  }
+  *out = nullptr;
+  int n = 0;
+  DW_CHECK_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) {
+    set_error("dw_ctx_create: device %d out of range (%d devices)", device, n);
+    return DW_EINVAL;
+  }
+  if (alloc && (!alloc->alloc || !alloc->release)) {
+    set_error("dw_ctx_create: allocator needs both alloc and release");
+    return DW_EINVAL;
+  }
+  DW_CHECK_HIP(hipSetDevice(device));
+  dw_ctx c = new (std::nothrow) dw_ctx_s;
+  if (!c) {
+    set_error("out of host memory");
+    return DW_ENOMEM;
+  }
+  c->device = device;
+  c->user_alloc = alloc != nullptr;
+  if (alloc) c->alloc = *alloc;
+  else memset(&c->alloc, 0, sizeof c->alloc);
+  *out = c;
+  return DW_OK;
+}
+
+dw_status dw_ctx_destroy(dw_ctx ctx) {
+  clear_error();
+  delete ctx;
+  return DW_OK;
+}
+
+dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4], const double* U_dev,
+                          hipStream_t stream, dw_field* out) {
+  clear_error();
+  if (!ctx || !L || !block || !U_dev || !out) {
+    set_error("dw_field_create: null argument");
+    return DW_EINVAL;
+  }
+  *out = nullptr;
+  Geom g;
+  int Li[4] = {L[0], L[1], L[2], L[3]}, Bi[4] = {block[0], block[1], block[2], block[3]};
+  if (const char* msg = make_geom(Li, Bi, &g)) {
+    set_error("dw_field_create: %s (L = %d %d %d %d, block = %d %d %d %d)", msg, L[0], L[1], L[2], L[3], block[0],
+              block[1], block[2], block[3]);
+    return DW_EINVAL;
+  }
+  DW_TRY(check_device(ctx));
+  dw_field f = new (std::nothrow) dw_field_s;
+  if (!f) {
+    set_error("out of host memory");
+    return DW_ENOMEM;
+  }
+  f->ctx = ctx;
+  f->g = g;
+  for (int p = 0; p < 4; ++p) f->U[p] = nullptr;
+  for (int p = 0; p < 4; ++p) {
+    size_t bytes = (size_t)g.V * 36 * pair_bytes(p);
+    f->U[p] = dev_alloc(ctx, bytes, stream);
+    if (!f->U[p]) {
+      for (int q = 0; q < p; ++q) dev_free(ctx, f->U[q], stream);
+      delete f;
+      set_error("dw_field_create: allocation of %zu bytes failed", bytes);
+      return DW_ENOMEM;
+    }
+    dw_status st = launch_pack_gauge(g, p, U_dev, f->U[p], stream);
+    if (st != DW_OK) {
+      for (int q = 0; q <= p; ++q) dev_free(ctx, f->U[q], stream);
+      delete f;
+      return st;
+    }
+  }
+  *out = f;
+  return DW_OK;
+}
+
+dw_status dw_field_destroy(dw_field f) {
+  clear_error();
+  if (!f) return DW_OK;
+  for (int p = 0; p < 4; ++p) dev_free(f->ctx, f->U[p], nullptr);
+  delete f;
+  return DW_OK;
+}
+
+int64_t dw_field_volume(dw_field f) { return f ? (int64_t)f->g.V : 0; }
+
+size_t dw_internal_bytes(dw_field f, int32_t prec, int32_t nrhs) {
+  if (!f || prec < 0 || prec > 3 || nrhs < 0) return 0;
+  return (size_t)f->g.V * 12 * pair_bytes(prec) * (size_t)nrhs;
+}
+
+dw_status dw_apply(dw_field f, double m0, const double* x, double* y, int32_t nrhs, hipStream_t stream) {
+  clear_error();
+  if (!f || !x || !y || nrhs < 0) {
+    set_error("dw_apply: invalid argument");
+    return DW_EINVAL;
+  }
+  if (nrhs == 0) return DW_OK;
+  if (x == y) {
+    set_error("dw_apply: x and y must not overlap");
+    return DW_EINVAL;
+  }
+  DW_TRY(check_device(f->ctx));
+  const Geom& g = f->g;
+  const size_t n = (size_t)g.V * 12;
+  DevBuf xi, yi;
+  DW_TRY(xi.alloc(f->ctx, n * 16 * nrhs, stream));
+  DW_TRY(yi.alloc(f->ctx, n * 16 * nrhs, stream));
+  DW_TRY(launch_pack_spinor(g, DW_PREC_F64, x, xi.p, 1.0, nrhs, stream));
+  DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, xi.p, 1.0, f->U[DW_PREC_F64], yi.as<double>(), nullptr, 0, nrhs,
+                             (long long)n, (long long)n, stream));
+  DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, yi.p, y, 1.0, nrhs, stream));
+  DW_CHECK_HIP(hipStreamSynchronize(stream));
+  return DW_OK;
+}
+
+dw_status dw_apply_ex(dw_field f, double m0, int32_t prec, const void* x, void* y, int32_t nrhs, hipStream_t stream) {
+  clear_error();
+  if (!f || !x || !y || nrhs < 0 || prec < 0 || prec > 3 || x == y) {
+    set_error("dw_apply_ex: invalid argument");
+    return DW_EINVAL;
+  }
+  if (nrhs == 0) return DW_OK;
+  DW_TRY(check_device(f->ctx));
+  return launch_dslash_lowp(f->g, m0, prec, x, f->U[prec], y, nrhs, stream);
+}
+
+dw_status dw_pack(dw_field f, int32_t prec, const double* x, void* xi, int32_t nrhs, hipStream_t stream) {
+  clear_error();
+  if (!f || !x || !xi || nrhs < 0 || prec < 0 || prec > 3) {
+    set_error("dw_pack: invalid argument");
+    return DW_EINVAL;
+  }
+  if (nrhs == 0) return DW_OK;
+  DW_TRY(check_device(f->ctx));
+  return launch_pack_spinor(f->g, prec, x, xi, 1.0, nrhs, stream);
+}
+
+dw_status dw_unpack(dw_field f, int32_t prec, const void* xi, double* x, int32_t nrhs, hipStream_t stream) {
+  clear_error();
+  if (!f || !x || !xi || nrhs < 0 || prec < 0 || prec > 3) {
+    set_error("dw_unpack: invalid argument");
+    return DW_EINVAL;
+  }
+  if (nrhs == 0) return DW_OK;
+  DW_TRY(check_device(f->ctx));
+  return launch_unpack_spinor(f->g, prec, xi, x, 1.0, nrhs, stream);
+}
+
+}  // extern "C"
+
+namespace dw {
+
+dw_status check_sap_params(const Geom& g, const sap_params* sp) {
+  if (!sp) {
+    set_error("null sap_params");
+    return DW_EINVAL;
+  }
+  for (int mu = 0; mu < 4; ++mu)
+    if (sp->block[mu] != g.B[mu]) {
+      set_error("sap block %d %d %d %d differs from the field's block %d %d %d %d", sp->block[0], sp->block[1],
+                sp->block[2], sp->block[3], g.B[0], g.B[1], g.B[2], g.B[3]);
+      return DW_EINVAL;
+    }
+  if (sp->ncycles < 0 || sp->nmr < 0 || sp->storage < 0 || sp->storage > 3) {
+    set_error("invalid sap_params (ncycles %d, nmr %d, storage %d)", sp->ncycles, sp->nmr, sp->storage);
+    return DW_EINVAL;
+  }
+  return DW_OK;
+}
+
+// z (accumulator, FP64 for F64 storage else FP32) = M v, where v is already
+// at storage precision in the internal layout. nrhs fields, stride V*12.
+dw_status sap_apply_internal(dw_field f, double m0, const sap_params* sp, const void* v, void* z, int nrhs,
+                             hipStream_t stream) {
+  const Geom& g = f->g;
+  const int prec = sp->storage;
+  const long long n = g.V * 12;
+  for (int cyc = 0; cyc < sp->ncycles; ++cyc)
+    for (int colour = 0; colour < 2; ++colour)
+      DW_TRY(launch_sap_colour(g, m0, prec, v, z, f->U[prec], colour, sp->nmr, cyc == 0 && colour == 0 ? 1 : 0, nrhs,
+                               n, n, stream));
+  return DW_OK;
+}
+
+}  // namespace dw
+
+extern "C" dw_status sap_precondition(dw_field f, double m0, const sap_params* sp, const double* v, double* z,
+                                      int32_t nrhs, hipStream_t stream) {
+  clear_error();
+  if (!f || !v || !z || nrhs < 0 || v == z) {
+    set_error("sap_precondition: invalid argument");
+    return DW_EINVAL;
+  }
+  DW_TRY(check_sap_params(f->g, sp));
+  if (nrhs == 0) return DW_OK;
+  DW_TRY(check_device(f->ctx));
+  const Geom& g = f->g;
+  const long long n = g.V * 12;
+  const int prec = sp->storage;
+  const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
+  if (sp->ncycles == 0) {
+    DW_CHECK_HIP(hipMemsetAsync(z, 0, (size_t)n * 16 * nrhs, stream));
+    DW_CHECK_HIP(hipStreamSynchronize(stream));
+    return DW_OK;
+  }
+  DevBuf vi, zi, part, nrm;
+  DW_TRY(vi.alloc(f->ctx, (size_t)n * pair_bytes(prec), stream));
+  DW_TRY(zi.alloc(f->ctx, (size_t)n * pair_bytes(zprec), stream));
+  DW_TRY(part.alloc(f->ctx, (size_t)kBlasGrid * 16, stream));
+  DW_TRY(nrm.alloc(f->ctx, 16, stream));
+  for (int r = 0; r < nrhs; ++r) {
+    const double* vr = v + 2 * (long long)r * n;
+    double* zr = z + 2 * (long long)r * n;
+    // M is scale-equivariant (M(a v) = a M(v)); low-precision storage gets
+    // v scaled to unit RMS per entry so that FP16 keeps its range.
+    double sigma = 1.0;
+    if (prec != DW_PREC_F64) {
+      DW_TRY(blas_dots(DW_PREC_F64, vr, n, 1, vr, n, part.as<double>(), nrm.as<double>(), 1, 0, stream));
+      double h[2];
+      DW_CHECK_HIP(hipMemcpyAsync(h, nrm.p, sizeof h, hipMemcpyDeviceToHost, stream));
+      DW_CHECK_HIP(hipStreamSynchronize(stream));
+      if (h[0] > 0) sigma = sqrt((double)n / h[0]);
+    }
+    DW_TRY(launch_pack_spinor(g, prec, vr, vi.p, sigma, 1, stream));
+    DW_TRY(sap_apply_internal(f, m0, sp, vi.p, zi.p, 1, stream));
+    DW_TRY(launch_unpack_spinor(g, zprec, zi.p, zr, 1.0 / sigma, 1, stream));
+  }
+  DW_CHECK_HIP(hipStreamSynchronize(stream));
+  return DW_OK;
+}

@@ -54,13 +54,35 @@ def _gauss_complex(rng, shape):
     return (x[..., 0] + 1j * x[..., 1]) * (1.0 / math.sqrt(2.0))
 
 
+def _traceless_hermitian(A):
+    H = 0.5 * (A + np.conj(np.swapaxes(A, -1, -2)))
+    tr = np.trace(H, axis1=-2, axis2=-1).real / 3.0
+    return H - tr[..., None, None] * np.eye(3)
+
+
+def exp_i_eps_h_eigh(A, eps):
+    """exp(i eps H) through eigh(H) (reference form, used in tests)."""
+    d, W = np.linalg.eigh(_traceless_hermitian(A))
+    ph = np.exp(1j * eps * d)
+    return np.matmul(W * ph[..., None, :], np.conj(np.swapaxes(W, -1, -2)))
+
+
+def exp_i_eps_h(A, eps):
+    """exp(i eps H), H the traceless Hermitian part of A, by PyTorch's CPU
+    matrix exponential (multi-threaded; equals the eigh form to rounding)."""
+    import torch
+
+    X = torch.from_numpy(np.ascontiguousarray((1j * eps) * _traceless_hermitian(A)))
+    return torch.linalg.matrix_exp(X).numpy()
+
+
 def gauge_field(L, eps, seed, t_chunk=None):
     """Random SU(3) links U_mu(n) = exp(i*eps*H), H traceless Hermitian Gaussian.
 
     Stream: ``numpy.random.default_rng(seed)`` draws X of shape
     (4, Lt, Lz, Ly, Lx, 3, 3, 2) in C order (generated in chunks along the
     leading axes, which consumes the same stream). A = (X0 + i X1)/sqrt(2),
-    H = (A + A^H)/2 - tr/3, U = W diag(exp(i eps d)) W^H from eigh(H).
+    H = (A + A^H)/2 - tr/3, U = exp(i eps H).
     """
     shp = lattice_shape(L)
     Lt = shp[0]
@@ -69,17 +91,11 @@ def gauge_field(L, eps, seed, t_chunk=None):
     if t_chunk is None:
         sites_per_t = int(np.prod(shp[1:]))
         t_chunk = max(1, min(Lt, (1 << 20) // max(1, sites_per_t)))
-    eye = np.eye(3)
     for mu in range(4):
         for t0 in range(0, Lt, t_chunk):
             t1 = min(Lt, t0 + t_chunk)
             A = _gauss_complex(rng, (t1 - t0,) + shp[1:] + (3, 3))
-            H = 0.5 * (A + np.conj(np.swapaxes(A, -1, -2)))
-            tr = np.trace(H, axis1=-2, axis2=-1).real / 3.0
-            H = H - tr[..., None, None] * eye
-            d, W = np.linalg.eigh(H)
-            ph = np.exp(1j * eps * d)
-            U[mu, t0:t1] = np.matmul(W * ph[..., None, :], np.conj(np.swapaxes(W, -1, -2)))
+            U[mu, t0:t1] = exp_i_eps_h(A, eps)
     return U
 
 

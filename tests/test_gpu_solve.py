@@ -1,0 +1,116 @@
+"""GPU FGMRES-DR (Alg. 4) against the FP64 oracle.
+
+  * the all-FP64 GPU solve follows the oracle's iteration (same Arnoldi
+    steps up to rounding: classical GS with reorthogonalisation on the GPU,
+    modified GS in the oracle) and reaches the same solution;
+  * mixed precision (FP32/FP16/BF16 SAP, FP64 outer) reaches the 1e-10
+    true residual, checked with the oracle's operator, and the oracle's
+    solution within the conditioning bound;
+  * control flow: k = 0 is FGMRES(m); a threshold t < 1 forces a clean
+    restart every cycle, which reproduces FGMRES(m); max_iter gives
+    NotConverged with the last iterate; b = 0 gives x = 0; bad parameters
+    are rejected.
+"""
+import numpy as np
+import pytest
+
+import paper_1204_5463_amd as P
+import synth
+from oracle import fgmresdr as F
+from oracle import sap as S
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+# the 8^4 plain-method configuration: eps 0.3, m0 -0.1, 4^4 blocks, 1 SAP
+# cycle, 4 MR steps, FGMRES-DR(20, 5), tol 1e-10
+L1, B1, EPS1, M01 = (8, 8, 8, 8), (4, 4, 4, 4), 0.3, -0.1
+
+
+@pytest.fixture(scope="module")
+def c1(dwctx):
+    U = synth.gauge_field(L1, EPS1, 0)
+    b = synth.gaussian_spinor(L1, 1000)
+    f = P.Field(dwctx, L1, B1, P.to_device(U))
+    shp = b.shape
+    A = lambda v: W.apply_D(U, M01, v.reshape(shp)).reshape(-1)
+    M = lambda v: S.sap(U, M01, L1, B1, 1, 4, v.reshape(shp)).reshape(-1)
+    xo, info = F.fgmresdr(A, M, b.reshape(-1), 20, 5, tol=1e-10, max_iter=2000)
+    return U, b, f, xo.reshape(shp), info
+
+
+def _params(prec=P.DW_PREC_F64, m=20, k=5, tol=1e-10, max_iter=2000, t=5.0, ncyc=1, nmr=4, block=B1):
+    return P.SolverParams(m=m, k=k, max_iter=max_iter, tol=tol, restart_t=t,
+                          sap=P.SapParams(block=block, ncycles=ncyc, nmr=nmr, storage=prec))
+
+
+def test_fp64_solve_follows_oracle(c1):
+    U, b, f, xo, info = c1
+    x, st = f.solve(M01, _params(), P.to_device(b))
+    x = x.cpu().numpy()
+    st = st[0]
+    assert st.converged and st.true_relres <= 1e-10
+    assert abs(st.iterations - info.iterations) <= 1, (st.iterations, info.iterations)
+    assert st.cycles == info.cycles and st.clean_restarts == info.clean_restarts == 0
+    r = b - W.apply_D(U, M01, x)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("prec", [P.DW_PREC_F32, P.DW_PREC_F16, P.DW_PREC_BF16])
+def test_mixed_precision_solve(c1, prec):
+    U, b, f, xo, info = c1
+    x, st = f.solve(M01, _params(prec), P.to_device(b))
+    x = x.cpu().numpy()
+    st = st[0]
+    assert st.converged
+    r = b - W.apply_D(U, M01, x)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b) * 1.01
+    # |lambda_min| of D is about 0.1 here: error <= cond * residual
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert st.iterations <= 2 * info.iterations
+
+
+def test_k0_and_forced_clean_restarts_are_fgmres(c1):
+    U, b, f, xo, info = c1
+    _, s0 = f.solve(M01, _params(k=0, m=10), P.to_device(b))
+    _, s1 = f.solve(M01, _params(k=4, m=10, t=0.5), P.to_device(b))
+    s0, s1 = s0[0], s1[0]
+    assert s0.converged and s1.converged
+    assert s0.iterations == s1.iterations and s0.cycles == s1.cycles
+    assert s0.clean_restarts == 0 and s1.clean_restarts == s1.cycles - 1
+    shp = b.shape
+    A = lambda v: W.apply_D(U, M01, v.reshape(shp)).reshape(-1)
+    M = lambda v: S.sap(U, M01, L1, B1, 1, 4, v.reshape(shp)).reshape(-1)
+    _, i0 = F.fgmresdr(A, M, b.reshape(-1), 10, 0, tol=1e-10, max_iter=2000)
+    assert abs(i0.iterations - s0.iterations) <= 1
+
+
+def test_not_converged_and_trivial_rhs(c1, dwctx):
+    U, b, f, xo, info = c1
+    x, st = f.solve(M01, _params(max_iter=7), P.to_device(b), raise_on_notconv=False)
+    assert not st[0].converged and st[0].iterations == 7
+    r = b - W.apply_D(U, M01, x.cpu().numpy())
+    assert abs(np.linalg.norm(r) / np.linalg.norm(b) - st[0].true_relres) < 1e-8
+    with pytest.raises(P.NotConverged):
+        f.solve(M01, _params(max_iter=3), P.to_device(b))
+    z = np.zeros_like(b)
+    x0, s0 = f.solve(M01, _params(), P.to_device(z))
+    assert s0[0].converged and np.count_nonzero(x0.cpu().numpy()) == 0
+    for bad in (_params(k=20), _params(m=60), _params(tol=0.0), _params(block=(2, 2, 2, 2))):
+        with pytest.raises(P.DwError) as e:
+            f.solve(M01, bad, P.to_device(b))
+        assert e.value.status == P.DW_EINVAL
+
+
+def test_multi_rhs_matches_single(c1):
+    U, b, f, xo, info = c1
+    bb = np.stack([b, synth.gaussian_spinor(L1, 1001)])
+    x, st = f.solve(M01, _params(P.DW_PREC_F32), P.to_device(bb))
+    x = x.cpu().numpy()
+    for r in range(2):
+        assert st[r].converged
+        res = bb[r] - W.apply_D(U, M01, x[r])
+        assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(bb[r])
+    x1, _ = f.solve(M01, _params(P.DW_PREC_F32), P.to_device(bb[1]))
+    assert np.linalg.norm(x1.cpu().numpy() - x[1]) <= 1e-9 * np.linalg.norm(x[1])

@@ -18,6 +18,13 @@ def test_gauge_field_is_su3_and_chunk_independent():
     assert not np.array_equal(U1, synth.gauge_field(L, 0.7, seed=4))
 
 
+def test_taylor_exponential_equals_eigh_form():
+    rng = np.random.default_rng(5)
+    A = (rng.standard_normal((2000, 3, 3)) + 1j * rng.standard_normal((2000, 3, 3))) / np.sqrt(2)
+    for eps in (0.3, 0.7, 1.0):
+        assert np.max(np.abs(synth.exp_i_eps_h(A, eps) - synth.exp_i_eps_h_eigh(A, eps))) < 1e-14
+
+
 def test_spinors_and_sources():
     L = (2, 2, 2, 4)
     a = synth.gaussian_spinor(L, 1000)
