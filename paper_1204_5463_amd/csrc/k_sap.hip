@@ -9,6 +9,8 @@
 //      alpha = (p^H rho) / (p^H p) over the block's sites, with the
 //      residual rho kept in LDS so that neighbours can read it;
 //   3. z += y on the block.
+// With z_zero set (first colour of the first cycle) z is not read and is
+// initialised here: y on this colour's blocks, zero on the other colour's.
 // Same-colour blocks never read each other's z, so updating z in place is
 // race-free. Arithmetic is T (float for FP32/FP16/BF16 storage, double for
 // FP64 storage); the block inner products are wavefront reductions followed
@@ -118,6 +120,13 @@ __global__ void __launch_bounds__(MAXT)
     for (int c = 0; c < 12; ++c) {
       const long long idx = spinor_index(g, b, c, l);
       st(zr + idx, z_zero ? y[c] : ld<T>(zr + idx) + y[c]);
+    }
+    // z starts at zero: this workgroup also clears one block of the other
+    // colour (same count per colour), which this launch never reads
+    if (z_zero) {
+      const int bo = (1 - colour) * g.nbc + blockIdx.x;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) st(zr + spinor_index(g, bo, c, l), mk<T>(0, 0));
     }
   }
 }
