@@ -178,6 +178,40 @@ dw_status sap_precondition(dw_field field, double m0, const sap_params* sap, con
 dw_status fgmresdr_solve(dw_field field, double m0, const fgmresdr_params* params, const double* b, double* x,
                          int32_t nrhs, dw_solve_stats* stats, hipStream_t stream);
 
+/* ---- per-kernel-class timing ---------------------------------------------
+ * When enabled on a context, every kernel launch made for that context is
+ * bracketed by HIP events on the launch stream; elapsed times are resolved
+ * at the library's synchronisation points and accumulated per class
+ * together with the launch's algorithmic bytes (data the method must move:
+ * each operand read once, each result written once) and flops. */
+enum {
+  DW_K_DSLASH_F64 = 0,  /* FP64 operator of the outer solver (A z, explicit residual) */
+  DW_K_DSLASH_LOWP = 1, /* operator at storage precision (dw_apply_ex) */
+  DW_K_SAP = 2,         /* one SAP colour sweep (block residual + MR steps) */
+  DW_K_DOTS = 3,        /* multi-dot V^H w, first stage */
+  DW_K_REDUCE = 4,      /* multi-dot, second stage */
+  DW_K_SUBCOLS = 5,     /* w -= V h */
+  DW_K_SCALE = 6,       /* y = a x */
+  DW_K_COMBINE = 7,     /* x += Z eta */
+  DW_K_ROTATE = 8,      /* V <- V Q, Z <- Z Q_k */
+  DW_K_CONVERT = 9,     /* precision / layout conversion */
+  DW_K_DENSE = 10,      /* small dense FP64 kernels (one workgroup) */
+  DW_K_COUNT = 11
+};
+typedef struct dw_kernel_stats {
+  int64_t launches;
+  double ms;     /* summed event time */
+  double bytes;  /* summed algorithmic bytes */
+  double flops;  /* summed algorithmic flops */
+} dw_kernel_stats;
+
+/* Turns timing on (1) or off (0) for calls made with this context. */
+dw_status dw_profile_enable(dw_ctx ctx, int32_t on);
+/* Copies the accumulated statistics of kernel class kclass. */
+dw_status dw_profile_get(dw_ctx ctx, int32_t kclass, dw_kernel_stats* out);
+/* Clears the accumulated statistics. */
+dw_status dw_profile_reset(dw_ctx ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,18 +57,18 @@ P_PLUS = np.array([I4 + g for g in GAMMA])    # (1 + gamma_mu), backward hop
 
 
 def _colour_mul(U, x):
-    """(U x)(n)_{s,a} = sum_b U(n)_{ab} x(n)_{s,b}."""
-    return np.einsum("...ab,...sb->...sa", U, x)
+    """(U x)(n)_{s,a} = sum_b U(n)_{ab} x(n)_{s,b}, i.e. x(n) U(n)^T per site."""
+    return np.matmul(x, np.swapaxes(U, -1, -2))
 
 
 def _colour_mul_dag(U, x):
-    """(U^dagger x)(n)_{s,a} = sum_b conj(U(n)_{ba}) x(n)_{s,b}."""
-    return np.einsum("...ba,...sb->...sa", U.conj(), x)
+    """(U^dagger x)(n)_{s,a} = sum_b conj(U(n)_{ba}) x(n)_{s,b}, i.e. x(n) conj(U(n))."""
+    return np.matmul(x, U.conj())
 
 
 def _spin_mul(P, x):
     """(P x)(n)_{s,a} = sum_t P_{st} x(n)_{t,a}."""
-    return np.einsum("st,...ta->...sa", P, x)
+    return np.matmul(P, x)
 
 
 def hop_forward(U, x, mu):

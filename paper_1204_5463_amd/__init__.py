@@ -56,6 +56,15 @@ class _SolverParams(ctypes.Structure):
                 ("sap", _SapParams), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+KCLASS = {"dslash_f64": 0, "dslash_lowp": 1, "sap": 2, "dots": 3, "reduce": 4, "subcols": 5, "scale": 6,
+          "combine": 7, "rotate": 8, "convert": 9, "dense": 10}
+
+
+class _KStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
                 ("clean_restarts", ctypes.c_int32), ("true_relres", ctypes.c_double),
@@ -143,6 +152,9 @@ def load(path: str = LIB_PATH):
         "dw_unpack": (st, [vp, i32, vp, vp, i32, vp]),
         "sap_precondition": (st, [vp, dbl, ctypes.POINTER(_SapParams), vp, vp, i32, vp]),
         "fgmresdr_solve": (st, [vp, dbl, ctypes.POINTER(_SolverParams), vp, vp, i32, ctypes.POINTER(_Stats), vp]),
+        "dw_profile_enable": (st, [vp, i32]),
+        "dw_profile_get": (st, [vp, i32, ctypes.POINTER(_KStats)]),
+        "dw_profile_reset": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -205,6 +217,22 @@ class Context:
         _check(L.dw_ctx_create(device, ctypes.byref(self._alloc) if self._alloc else None, ctypes.byref(h)),
                "dw_ctx_create")
         self.handle = h
+
+    def profile(self, on: bool = True):
+        """Per-kernel-class HIP-event timing of every launch made for this context."""
+        _check(lib().dw_profile_enable(self.handle, 1 if on else 0), "dw_profile_enable")
+
+    def profile_reset(self):
+        _check(lib().dw_profile_reset(self.handle), "dw_profile_reset")
+
+    def profile_stats(self):
+        """{class name: dict(launches, ms, bytes, flops)} accumulated since the last reset."""
+        out = {}
+        for name, kc in KCLASS.items():
+            k = _KStats()
+            _check(lib().dw_profile_get(self.handle, kc, ctypes.byref(k)), "dw_profile_get")
+            out[name] = {"launches": int(k.launches), "ms": k.ms, "bytes": k.bytes, "flops": k.flops}
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -5,15 +5,33 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dwsap.h"
 #include "dw_geom.hpp"
+
+namespace dw {
+struct Profiler {
+  struct Rec {
+    int kc;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::mutex mu;
+  bool on = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  dw_kernel_stats acc[DW_K_COUNT] = {};
+};
+}  // namespace dw
 
 struct dw_ctx_s {
   int device;
   dw_allocator alloc;
   bool user_alloc;
+  dw::Profiler prof;
 };
 
 struct dw_field_s {
@@ -51,6 +69,25 @@ void clear_error();
     dw_status s_ = (expr);        \
     if (s_ != DW_OK) return s_;   \
   } while (0)
+
+// ---- kernel timing ----------------------------------------------------------------
+// The entry points install their context's profiler for the calling thread;
+// launchers bracket their kernels with KTimer.
+struct ProfScope {
+  Profiler* prev;
+  explicit ProfScope(dw_ctx ctx);
+  ~ProfScope();
+};
+struct KTimer {
+  Profiler* p = nullptr;
+  hipEvent_t a = nullptr;
+  hipStream_t s = nullptr;
+  int kc;
+  KTimer(int kclass, hipStream_t stream);
+  void done(double bytes, double flops);
+};
+// resolves finished timing records (of the calling thread's profiler if null)
+void prof_flush(Profiler* p = nullptr);
 
 // ---- device memory ------------------------------------------------------------
 void* dev_alloc(dw_ctx ctx, size_t bytes, hipStream_t stream);
@@ -97,8 +134,10 @@ dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* ou
 dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* out, double scale, int nrhs,
                                hipStream_t s);
 dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out, hipStream_t s);
-// elementwise out = scale * in over n pairs (precision conversion)
-dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s);
+// elementwise out = scale * (dscale ? dscale[0] : 1) * in over n pairs
+// (precision conversion; dscale is a device scalar)
+dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s,
+                         const double* dscale = nullptr);
 
 // y = scale * D x (mode 0) or y = b - scale * D x (mode 1), internal layout.
 // prec_x: DW_PREC_F64 or DW_PREC_F32 input with FP64 links/output/arithmetic

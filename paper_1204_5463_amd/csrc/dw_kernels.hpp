@@ -28,6 +28,17 @@ dw_status blas_combine(int prec_z, const void* Z, long long stride, int ncols, c
 dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const double* Q, int ldq, int nout, long long n,
                       hipStream_t s);
 
+// Gram-Schmidt with delayed reorthogonalisation (see k_blas.hip).
+// gs_reduce: out[0..2nv+3) = [V^H u | V^H w | u^H u, u^H w, w^H w] over the
+// nv final columns; u or w may be null. partials: (2 kMaxM + 5) * kBlasGrid pairs.
+dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, const double* w, long long n,
+                    double* partials, double* out, hipStream_t s);
+// gs_update: jcol >= 0: V_jcol <- (V_jcol - V a)/beta; w != null:
+// wout <- w - V b - c V_jcol (c only if jcol >= 0), nrm2 <- ||wout||^2.
+// coef as written by dense_gs_coef.
+dw_status gs_update(double* V, long long stride, int nv, int jcol, const double* w, double* wout, const double* coef,
+                    long long n, double* partials, double* nrm2, hipStream_t s);
+
 // ---- small dense FP64 (one workgroup) ---------------------------------------------
 // Scalars block written by dense_step / dense_cycle_end (doubles):
 enum {
@@ -54,6 +65,18 @@ dw_status dense_lsq(const double* H, int cols, const double* c, double* eta, dou
 // harmonic Ritz values sorted by modulus; scal[kSclStatus] = status.
 dw_status dense_deflate(double* H, int mm, int k, const double* c, const double* eta, double* Q, double* ritz,
                         double* scal, hipStream_t s);
+// Coefficients of one delayed-reorthogonalisation step from gs_reduce's
+// output red. hu: the lagged vector u = V_jcol is finalised: a = V^H u,
+// beta = sqrt(u^H u - |a|^2), H(0:jcol, jcol-1) += a, H(jcol, jcol-1) = beta.
+// hw: column jw of H gets its first-pass entries b (rows 0..nv-1) and
+// c = (u^H w - a^H b)/beta (row jcol) when hu. Writes coef for gs_update.
+dw_status dense_gs_coef(double* H, int nv, int jcol, int jw, int hu, int hw, const double* red, double* coef,
+                        double* scal, double bd_tol, hipStream_t s);
+// Completes step j after gs_update: H(j+1, j) = sqrt(nrm2), breakdown test,
+// implicit residual of the (j+2) x (j+1) least-squares problem; also
+// scal[kSclHinv] = 1/H(j+1, j) for scaling the next preconditioner input.
+dw_status dense_step2(double* H, int j, const double* nrm2, const double* c, double* scal, double bd_tol,
+                      hipStream_t s);
 // fresh start: scal[kSclBeta] = sqrt(nrm2.re), scal[kSclBetaInv] = 1/beta, c = beta e_1, H = 0
 dw_status dense_fresh(double* H, double* c, const double* nrm2, double* scal, hipStream_t s);
 

@@ -156,6 +156,133 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+
+// ---- Gram-Schmidt with delayed reorthogonalisation ---------------------------
+// One reduction sweep computes, over the final basis columns V_0..V_{nv-1},
+//   a = V^H u (u: the previous step's once-orthogonalised vector),
+//   b = V^H w (w: the new vector A z_j), and u^H u, u^H w, w^H w;
+// one update sweep forms v = (u - V a) / beta and w' = w - V b - c v.
+// Partial-sum slots: [0, nv) a, [nv, 2 nv) b, 2 nv: u^H u, 2 nv + 1: u^H w,
+// 2 nv + 2: w^H w.
+template <bool HU, bool HW>
+__global__ void __launch_bounds__(kThreads)
+    k_gs_reduce(const s64* __restrict__ V, long long stride, int c0, int nc, int nv, const s64* __restrict__ u,
+                const s64* __restrict__ w, long long n, int first, s64* __restrict__ partials) {
+  constexpr int NA = kDotCols;
+  __shared__ double red[kThreads / kWave][2 * NA + 3][2];
+  cplx<double> au[NA], aw[NA], uu = mk(0.0, 0.0), uw = mk(0.0, 0.0), ww = mk(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < NA; ++c) {
+    au[c] = mk(0.0, 0.0);
+    aw[c] = mk(0.0, 0.0);
+  }
+  const long long step = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) {
+    cplx<double> uv = mk(0.0, 0.0), wv = mk(0.0, 0.0);
+    if constexpr (HU) uv = ld<double>(u + i);
+    if constexpr (HW) wv = ld<double>(w + i);
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+      if (c < nc) {
+        const cplx<double> vc = ld<double>(V + (long long)(c0 + c) * stride + i);
+        if constexpr (HU) au[c] += cdot(vc, uv);
+        if constexpr (HW) aw[c] += cdot(vc, wv);
+      }
+    if (first) {
+      if constexpr (HU) uu.re += norm2(uv);
+      if constexpr (HU && HW) uw += cdot(uv, wv);
+      if constexpr (HW) ww.re += norm2(wv);
+    }
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  auto put = [&](int slot, cplx<double> v) {
+    const double re = wsum(v.re), im = wsum(v.im);
+    if (lane == 0) {
+      red[wave][slot][0] = re;
+      red[wave][slot][1] = im;
+    }
+  };
+#pragma unroll
+  for (int c = 0; c < NA; ++c) {
+    if (HU) put(c, au[c]);
+    if (HW) put(NA + c, aw[c]);
+  }
+  put(2 * NA, uu);
+  put(2 * NA + 1, uw);
+  put(2 * NA + 2, ww);
+  __syncthreads();
+  const int G = gridDim.x;
+  for (int t = threadIdx.x; t < 2 * NA + 3; t += kThreads) {
+    int slot;
+    if (t < NA) {
+      if (!HU || t >= nc) continue;
+      slot = c0 + t;
+    } else if (t < 2 * NA) {
+      if (!HW || t - NA >= nc) continue;
+      slot = nv + c0 + (t - NA);
+    } else {
+      if (!first) continue;
+      slot = 2 * nv + (t - 2 * NA);
+    }
+    double re = 0, im = 0;
+    for (int q = 0; q < kThreads / kWave; ++q) {
+      re += red[q][t][0];
+      im += red[q][t][1];
+    }
+    partials[(long long)slot * G + blockIdx.x] = s64{re, im};
+  }
+}
+
+// coef: a[0..nv), b[0..nv), c (slot 2 nv), 1/beta (slot 2 nv + 1, real part).
+// HU: V_jcol <- (V_jcol - V a) / beta (in place); HW: wout <- w - V b - c V_jcol,
+// partials[block] = sum |wout|^2 over the block's elements.
+template <bool HU, bool HW>
+__global__ void __launch_bounds__(kThreads)
+    k_gs_update(s64* __restrict__ V, long long stride, int nv, int jcol, const s64* __restrict__ w,
+                s64* __restrict__ wout, const s64* __restrict__ coef, long long n, s64* __restrict__ partials) {
+  __shared__ cplx<double> ca[kMaxM + 1], cb[kMaxM + 1];
+  __shared__ double red[kThreads / kWave];
+  for (int c = threadIdx.x; c < nv; c += kThreads) {
+    ca[c] = ld<double>(coef + c);
+    cb[c] = ld<double>(coef + nv + c);
+  }
+  __syncthreads();
+  const cplx<double> cj = ld<double>(coef + 2 * nv);
+  const double invbeta = coef[2 * nv + 1].x;
+  double nrm = 0;
+  const long long step = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) {
+    cplx<double> uu = mk(0.0, 0.0), wa = mk(0.0, 0.0);
+    if constexpr (HU) uu = ld<double>(V + (long long)jcol * stride + i);
+    if constexpr (HW) wa = ld<double>(w + i);
+    for (int c = 0; c < nv; ++c) {
+      const cplx<double> vc = ld<double>(V + (long long)c * stride + i);
+      if constexpr (HU) uu -= ca[c] * vc;
+      if constexpr (HW) wa -= cb[c] * vc;
+    }
+    if constexpr (HU) {
+      uu = invbeta * uu;
+      st(V + (long long)jcol * stride + i, uu);
+      if constexpr (HW) wa -= cj * uu;
+    }
+    if constexpr (HW) {
+      st(wout + i, wa);
+      nrm += norm2(wa);
+    }
+  }
+  if constexpr (HW) {
+    nrm = wsum(nrm);
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane == 0) red[wave] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int q = 0; q < kThreads / kWave; ++q) t += red[q];
+      partials[blockIdx.x] = s64{t, 0.0};
+    }
+  }
+}
+
 unsigned grid_for(long long n) {
   long long b = (n + kThreads - 1) / kThreads;
   if (b > kBlasGrid) b = kBlasGrid;
@@ -170,14 +297,18 @@ dw_status blas_dots(int prec_v, const void* V, long long stride, int ncols, cons
   for (int c0 = 0; c0 < ncols; c0 += kDotCols) {
     const int nc = ncols - c0 < kDotCols ? ncols - c0 : kDotCols;
     s64* part = (s64*)partials + (long long)c0 * G;
+    KTimer kt(DW_K_DOTS, s);
     if (prec_v == DW_PREC_F64)
       hipLaunchKernelGGL(k_dots<s64>, G, kThreads, 0, s, (const s64*)V + c0 * stride, stride, nc, (const s64*)w, n, part);
     else
       hipLaunchKernelGGL(k_dots<s32>, G, kThreads, 0, s, (const s32*)V + c0 * stride, stride, nc, (const s64*)w, n, part);
     DW_CHECK_LAUNCH();
+    kt.done((double)n * (nc * (double)pair_bytes(prec_v) + 16), (double)n * nc * 8);
   }
+  KTimer kr(DW_K_REDUCE, s);
   hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, ncols, (s64*)out, ostride, op);
   DW_CHECK_LAUNCH();
+  kr.done((double)G * ncols * 16, (double)G * ncols * 2);
   return DW_OK;
 }
 
@@ -187,14 +318,18 @@ dw_status blas_sub_cols(const double* V, long long stride, int ncols, const doub
     set_error("blas_sub_cols: too many columns");
     return DW_EINVAL;
   }
+  KTimer kt(DW_K_SUBCOLS, s);
   hipLaunchKernelGGL(k_sub_cols<s64>, grid_for(n), kThreads, 0, s, (const s64*)V, stride, ncols, (const s64*)h, (s64*)w, n);
   DW_CHECK_LAUNCH();
+  kt.done((double)n * (ncols + 2) * 16, (double)n * ncols * 8);
   return DW_OK;
 }
 
 dw_status blas_scale(const double* x, double* y, const double* alpha, long long n, hipStream_t s) {
+  KTimer kt(DW_K_SCALE, s);
   hipLaunchKernelGGL(k_scale, grid_for(n), kThreads, 0, s, (const s64*)x, (s64*)y, alpha, n);
   DW_CHECK_LAUNCH();
+  kt.done((double)n * 32, (double)n * 2);
   return DW_OK;
 }
 
@@ -204,11 +339,13 @@ dw_status blas_combine(int prec_z, const void* Z, long long stride, int ncols, c
     set_error("blas_combine: too many columns");
     return DW_EINVAL;
   }
+  KTimer kt(DW_K_COMBINE, s);
   if (prec_z == DW_PREC_F64)
     hipLaunchKernelGGL(k_combine<s64>, grid_for(n), kThreads, 0, s, (const s64*)Z, stride, ncols, (const s64*)coef, scale, (s64*)x, n);
   else
     hipLaunchKernelGGL(k_combine<s32>, grid_for(n), kThreads, 0, s, (const s32*)Z, stride, ncols, (const s64*)coef, scale, (s64*)x, n);
   DW_CHECK_LAUNCH();
+  kt.done((double)n * (ncols * (double)pair_bytes(prec_z) + 32), (double)n * ncols * 8);
   return DW_OK;
 }
 
@@ -218,11 +355,79 @@ dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const doub
     set_error("blas_rotate: unsupported shape %d -> %d", nin, nout);
     return DW_EINVAL;
   }
+  KTimer kt(DW_K_ROTATE, s);
   if (prec_v == DW_PREC_F64)
     hipLaunchKernelGGL(k_rotate<s64>, grid_for(n), kThreads, 0, s, (s64*)V, stride, nin, (const s64*)Q, ldq, nout, n);
   else
     hipLaunchKernelGGL(k_rotate<s32>, grid_for(n), kThreads, 0, s, (s32*)V, stride, nin, (const s64*)Q, ldq, nout, n);
   DW_CHECK_LAUNCH();
+  kt.done((double)n * (nin + nout) * pair_bytes(prec_v), (double)n * nin * nout * 8);
+  return DW_OK;
+}
+
+}  // namespace dw
+
+namespace dw {
+
+dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, const double* w, long long n,
+                    double* partials, double* out, hipStream_t s) {
+  const bool hu = u != nullptr, hw = w != nullptr;
+  if (nv < 0 || nv > kMaxM + 1 || (!hu && !hw)) {
+    set_error("gs_reduce: bad arguments");
+    return DW_EINVAL;
+  }
+  const unsigned G = grid_for(n);
+  const int nchunks = nv > 0 ? (nv + kDotCols - 1) / kDotCols : 1;
+  for (int q = 0; q < nchunks; ++q) {
+    const int c0 = q * kDotCols;
+    const int nc = nv - c0 < kDotCols ? nv - c0 : kDotCols;
+    KTimer kt(DW_K_DOTS, s);
+    const s64* Vp = (const s64*)V;
+    const s64 *up = (const s64*)u, *wp = (const s64*)w;
+    s64* part = (s64*)partials;
+    if (hu && hw)
+      hipLaunchKernelGGL((k_gs_reduce<true, true>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0, part);
+    else if (hu)
+      hipLaunchKernelGGL((k_gs_reduce<true, false>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0, part);
+    else
+      hipLaunchKernelGGL((k_gs_reduce<false, true>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0, part);
+    DW_CHECK_LAUNCH();
+    kt.done((double)n * 16 * (nc + (hu ? 1 : 0) + (hw ? 1 : 0)), (double)n * 8 * nc * ((hu ? 1 : 0) + (hw ? 1 : 0)));
+  }
+  KTimer kr(DW_K_REDUCE, s);
+  hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 2 * nv + 3, (s64*)out, 1, 0);
+  DW_CHECK_LAUNCH();
+  kr.done((double)G * (2 * nv + 3) * 16, 0);
+  return DW_OK;
+}
+
+dw_status gs_update(double* V, long long stride, int nv, int jcol, const double* w, double* wout, const double* coef,
+                    long long n, double* partials, double* nrm2, hipStream_t s) {
+  const bool hu = jcol >= 0, hw = w != nullptr;
+  if (nv < 0 || nv > kMaxM + 1 || (!hu && !hw)) {
+    set_error("gs_update: bad arguments");
+    return DW_EINVAL;
+  }
+  const unsigned G = grid_for(n);
+  KTimer kt(DW_K_SUBCOLS, s);
+  s64* Vp = (s64*)V;
+  if (hu && hw)
+    hipLaunchKernelGGL((k_gs_update<true, true>), G, kThreads, 0, s, Vp, stride, nv, jcol, (const s64*)w, (s64*)wout,
+                       (const s64*)coef, n, (s64*)partials);
+  else if (hu)
+    hipLaunchKernelGGL((k_gs_update<true, false>), G, kThreads, 0, s, Vp, stride, nv, jcol, (const s64*)w,
+                       (s64*)wout, (const s64*)coef, n, (s64*)partials);
+  else
+    hipLaunchKernelGGL((k_gs_update<false, true>), G, kThreads, 0, s, Vp, stride, nv, jcol, (const s64*)w,
+                       (s64*)wout, (const s64*)coef, n, (s64*)partials);
+  DW_CHECK_LAUNCH();
+  kt.done((double)n * 16 * (nv + (hu ? 2 : 0) + (hw ? 2 : 0)), (double)n * 8 * nv * ((hu ? 1 : 0) + (hw ? 1 : 0)));
+  if (hw) {
+    KTimer kr(DW_K_REDUCE, s);
+    hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 1, (s64*)nrm2, 1, 0);
+    DW_CHECK_LAUNCH();
+    kr.done((double)G * 16, 0);
+  }
   return DW_OK;
 }
 

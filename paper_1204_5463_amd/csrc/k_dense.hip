@@ -143,6 +143,83 @@ __global__ void __launch_bounds__(kL) k_step(double* H, int j, const double* h1,
   }
 }
 
+
+// Coefficients of a delayed-reorthogonalisation Gram-Schmidt step (see
+// dense_gs_coef in dw_kernels.hpp). red: reduced slots of gs_reduce.
+__global__ void __launch_bounds__(kL) k_gs_coef(double* H, int nv, int jcol, int jw, int hu, int hw,
+                                                const double* red, double* coef, double* scal) {
+  const int lane = threadIdx.x;
+  C a2sum{0, 0};
+  double a2 = 0;
+  C ab{0, 0};
+  for (int i = lane; i < nv; i += kL) {
+    const C ai = ldc(red, i), bi = ldc(red, nv + i);
+    if (hu) a2 += norm2(ai);
+    if (hu && hw) ab += cdot(ai, bi);
+  }
+  a2 = wave_sum(a2);
+  ab.re = wave_sum(ab.re);
+  ab.im = wave_sum(ab.im);
+  (void)a2sum;
+  double beta = 1.0, invbeta = 1.0;
+  if (hu) {
+    const double uu = red[2 * (2 * nv)];
+    const double b2 = uu - a2;
+    beta = b2 > 0 ? sqrt(b2) : 0.0;
+    invbeta = beta > 0 ? 1.0 / beta : 0.0;
+  }
+  for (int i = lane; i < nv; i += kL) {
+    const C ai = hu ? ldc(red, i) : C{0, 0};
+    const C bi = hw ? ldc(red, nv + i) : C{0, 0};
+    stc(coef, i, ai);
+    stc(coef, nv + i, bi);
+    if (hu && jcol >= 1) stc(H, i + (long long)(jcol - 1) * kLd, ldc(H, i + (long long)(jcol - 1) * kLd) + ai);
+    if (hw) stc(H, i + (long long)jw * kLd, bi);
+  }
+  if (lane == 0) {
+    C cj{0, 0};
+    if (hu && hw && beta > 0) {
+      const C uw = ldc(red, 2 * nv + 1);
+      cj = invbeta * (uw - ab);
+    }
+    if (hu && jcol >= 1) stc(H, jcol + (long long)(jcol - 1) * kLd, C{beta, 0.0});
+    if (hu && hw) stc(H, jcol + (long long)jw * kLd, cj);
+    stc(coef, 2 * nv, cj);
+    stc(coef, 2 * nv + 1, C{invbeta, 0.0});
+    scal[kSclBeta] = beta;
+  }
+}
+
+__global__ void __launch_bounds__(kL) k_step2(double* H, int j, const double* nrm2, const double* c, double* scal,
+                                              double bd_tol) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  StepSmem& S = *reinterpret_cast<StepSmem*>(smem_raw);
+  const int lane = threadIdx.x;
+  const int rows = j + 2, cols = j + 1;
+  const double hn = sqrt(fmax(nrm2[0], 0.0));
+  if (lane == 0) stc(H, j + 1 + (long long)j * kLd, C{hn, 0.0});
+  __syncthreads();
+  __threadfence_block();
+  double part = 0;
+  for (int t = lane; t < rows * cols; t += kL) {
+    const int i = t % rows, q = t / rows;
+    const C v = (i == j + 1 && q == j) ? C{hn, 0.0} : ldc(H, i + (long long)q * kLd);
+    S.A[i + q * kLd] = v;
+    part += norm2(v);
+  }
+  if (lane < rows) S.rhs[lane] = ldc(c, lane);
+  const double hnorm = sqrt(wave_sum(part));
+  __syncthreads();
+  const bool broke = !(hn > bd_tol * hnorm);
+  hh_qr(S.A, kLd, rows, cols, S.rhs, S.Uv, kLd, S.beta);
+  if (lane == 0) {
+    scal[kSclHnext] = hn;
+    scal[kSclHinv] = broke ? 0.0 : 1.0 / hn;
+    scal[kSclResImp] = cabs(S.rhs[rows - 1]);
+    scal[kSclBreak] = broke ? 1.0 : 0.0;
+  }
+}
+
 __global__ void __launch_bounds__(kL) k_lsq(const double* H, int cols, const double* c, double* eta, double* scal) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   StepSmem& S = *reinterpret_cast<StepSmem*>(smem_raw);
@@ -530,8 +607,10 @@ dw_status dense_step(double* H, int j, const double* h1, const double* h2, const
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_step, sizeof(StepSmem)));
+  KTimer kt(DW_K_DENSE, s);
   hipLaunchKernelGGL(k_step, 1, kL, sizeof(StepSmem), s, H, j, h1, h2, nrm2, c, scal, bd_tol);
   DW_CHECK_LAUNCH();
+  kt.done(0, 0);
   return DW_OK;
 }
 
@@ -541,8 +620,10 @@ dw_status dense_lsq(const double* H, int cols, const double* c, double* eta, dou
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_lsq, sizeof(StepSmem)));
+  KTimer kt(DW_K_DENSE, s);
   hipLaunchKernelGGL(k_lsq, 1, kL, sizeof(StepSmem), s, H, cols, c, eta, scal);
   DW_CHECK_LAUNCH();
+  kt.done(0, 0);
   return DW_OK;
 }
 
@@ -553,14 +634,46 @@ dw_status dense_deflate(double* H, int mm, int k, const double* c, const double*
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_deflate, sizeof(DeflSmem)));
+  KTimer kt(DW_K_DENSE, s);
   hipLaunchKernelGGL(k_deflate, 1, kL, sizeof(DeflSmem), s, H, mm, k, c, eta, Q, ritz, scal);
   DW_CHECK_LAUNCH();
+  kt.done(0, 0);
+  return DW_OK;
+}
+
+dw_status dense_gs_coef(double* H, int nv, int jcol, int jw, int hu, int hw, const double* red, double* coef,
+                        double* scal, double bd_tol, hipStream_t s) {
+  (void)bd_tol;
+  if (nv < 0 || nv > kLd || jcol > kMaxM || jw >= kMaxM || (hw && jw < 0) || (hu && jcol < 0)) {
+    set_error("dense_gs_coef: bad sizes (nv %d, jcol %d, jw %d)", nv, jcol, jw);
+    return DW_EINVAL;
+  }
+  KTimer kt(DW_K_DENSE, s);
+  hipLaunchKernelGGL(k_gs_coef, 1, kL, 0, s, H, nv, jcol, jw, hu, hw, red, coef, scal);
+  DW_CHECK_LAUNCH();
+  kt.done(0, 0);
+  return DW_OK;
+}
+
+dw_status dense_step2(double* H, int j, const double* nrm2, const double* c, double* scal, double bd_tol,
+                      hipStream_t s) {
+  if (j < 0 || j >= kMaxM) {
+    set_error("dense_step2: column %d out of range", j);
+    return DW_EINVAL;
+  }
+  DW_TRY(set_lds(k_step2, sizeof(StepSmem)));
+  KTimer kt(DW_K_DENSE, s);
+  hipLaunchKernelGGL(k_step2, 1, kL, sizeof(StepSmem), s, H, j, nrm2, c, scal, bd_tol);
+  DW_CHECK_LAUNCH();
+  kt.done(0, 0);
   return DW_OK;
 }
 
 dw_status dense_fresh(double* H, double* c, const double* nrm2, double* scal, hipStream_t s) {
+  KTimer kt(DW_K_DENSE, s);
   hipLaunchKernelGGL(k_fresh, 1, kL, 0, s, H, c, nrm2, scal);
   DW_CHECK_LAUNCH();
+  kt.done(0, 0);
   return DW_OK;
 }
 

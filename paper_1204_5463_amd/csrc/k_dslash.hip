@@ -17,6 +17,9 @@ namespace dw {
 namespace {
 
 constexpr int kThreads = 256;
+// flops of one site of D: 8 hops x (12 projection + 2 x 66 SU(3) x vector
+// + 24 accumulation) - 24 (first accumulation is a copy) + 48 (diagonal)
+constexpr double kFlopsPerSite = 1368.0;
 
 // MODE 0: y = scale * D x ; MODE 1: y = b - scale * D x
 template <typename T, typename SX, typename SG, typename SY, int MODE>
@@ -61,6 +64,7 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
   s64* yo = (s64*)y;
   const s64* bo = (const s64*)b;
   dim3 grid = grid_for(g, nrhs);
+  KTimer kt(DW_K_DSLASH_F64, s);
   if (prec_x == DW_PREC_F64) {
     const s64* xi = (const s64*)x;
     if (mode == 0)
@@ -78,6 +82,8 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
     return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
+  kt.done((double)g.V * nrhs * (12.0 * pair_bytes(prec_x) + 36 * 16 + 12 * 16 + (mode == 1 ? 12 * 16 : 0)),
+          (double)g.V * nrhs * kFlopsPerSite);
   return DW_OK;
 }
 
@@ -85,6 +91,7 @@ dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, 
                              hipStream_t s) {
   dim3 grid = grid_for(g, nrhs);
   const long long st = g.V * 12;
+  KTimer kt(DW_K_DSLASH_LOWP, s);
   switch (prec) {
     case DW_PREC_F64:
       hipLaunchKernelGGL((k_dslash<double, s64, s64, s64, 0>), grid, kThreads, 0, s, g, 4.0 + m0, (const s64*)x, 1.0,
@@ -105,6 +112,7 @@ dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, 
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
+  kt.done((double)g.V * nrhs * 60.0 * pair_bytes(prec), (double)g.V * nrhs * kFlopsPerSite);
   return DW_OK;
 }
 

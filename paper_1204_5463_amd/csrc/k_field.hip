@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(kThreads) k_pack_gauge(Geom g, const s64* __re
 
 template <typename SI, typename SO>
 __global__ void __launch_bounds__(kThreads) k_convert(const SI* __restrict__ in, SO* __restrict__ out, double scale,
-                                                      long long n) {
+                                                      const double* __restrict__ dscale, long long n) {
+  if (dscale) scale *= dscale[0];
   long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
   const long long stride = (long long)gridDim.x * kThreads;
   for (; i < n; i += stride) st(out + i, scale * ld<double>(in + i));
@@ -75,6 +76,7 @@ dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* ou
                              hipStream_t s) {
   const s64* src = reinterpret_cast<const s64*>(in);
   dim3 grid = site_grid(g, nrhs);
+  KTimer kt(DW_K_CONVERT, s);
   switch (prec) {
     case DW_PREC_F64: hipLaunchKernelGGL(k_pack_spinor<s64>, grid, kThreads, 0, s, g, src, (s64*)out, scale); break;
     case DW_PREC_F32: hipLaunchKernelGGL(k_pack_spinor<s32>, grid, kThreads, 0, s, g, src, (s32*)out, scale); break;
@@ -83,6 +85,7 @@ dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* ou
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
+  kt.done((double)g.V * 12 * nrhs * (16 + pair_bytes(prec)), 0);
   return DW_OK;
 }
 
@@ -90,6 +93,7 @@ dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* 
                                hipStream_t s) {
   s64* dst = reinterpret_cast<s64*>(out);
   dim3 grid = site_grid(g, nrhs);
+  KTimer kt(DW_K_CONVERT, s);
   switch (prec) {
     case DW_PREC_F64: hipLaunchKernelGGL(k_unpack_spinor<s64>, grid, kThreads, 0, s, g, (const s64*)in, dst, scale); break;
     case DW_PREC_F32: hipLaunchKernelGGL(k_unpack_spinor<s32>, grid, kThreads, 0, s, g, (const s32*)in, dst, scale); break;
@@ -98,12 +102,14 @@ dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* 
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
+  kt.done((double)g.V * 12 * nrhs * (16 + pair_bytes(prec)), 0);
   return DW_OK;
 }
 
 dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out, hipStream_t s) {
   const s64* src = reinterpret_cast<const s64*>(in);
   dim3 grid = site_grid(g, 1);
+  KTimer kt(DW_K_CONVERT, s);
   switch (prec) {
     case DW_PREC_F64: hipLaunchKernelGGL(k_pack_gauge<s64>, grid, kThreads, 0, s, g, src, (s64*)out); break;
     case DW_PREC_F32: hipLaunchKernelGGL(k_pack_gauge<s32>, grid, kThreads, 0, s, g, src, (s32*)out); break;
@@ -112,32 +118,37 @@ dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
+  kt.done((double)g.V * 36 * (16 + pair_bytes(prec)), 0);
   return DW_OK;
 }
 
 namespace {
 template <typename SI>
-dw_status convert_from(const SI* in, int pout, void* out, double scale, long long n, hipStream_t s) {
+dw_status convert_from(const SI* in, int pout, void* out, double scale, const double* ds, long long n,
+                       hipStream_t s) {
   long long nb = (n + kThreads - 1) / kThreads;
   unsigned grid = (unsigned)(nb < 8192 ? (nb > 0 ? nb : 1) : 8192);
+  KTimer kt(DW_K_CONVERT, s);
   switch (pout) {
-    case DW_PREC_F64: hipLaunchKernelGGL((k_convert<SI, s64>), grid, kThreads, 0, s, in, (s64*)out, scale, n); break;
-    case DW_PREC_F32: hipLaunchKernelGGL((k_convert<SI, s32>), grid, kThreads, 0, s, in, (s32*)out, scale, n); break;
-    case DW_PREC_F16: hipLaunchKernelGGL((k_convert<SI, s16>), grid, kThreads, 0, s, in, (s16*)out, scale, n); break;
-    case DW_PREC_BF16: hipLaunchKernelGGL((k_convert<SI, sbf>), grid, kThreads, 0, s, in, (sbf*)out, scale, n); break;
+    case DW_PREC_F64: hipLaunchKernelGGL((k_convert<SI, s64>), grid, kThreads, 0, s, in, (s64*)out, scale, ds, n); break;
+    case DW_PREC_F32: hipLaunchKernelGGL((k_convert<SI, s32>), grid, kThreads, 0, s, in, (s32*)out, scale, ds, n); break;
+    case DW_PREC_F16: hipLaunchKernelGGL((k_convert<SI, s16>), grid, kThreads, 0, s, in, (s16*)out, scale, ds, n); break;
+    case DW_PREC_BF16: hipLaunchKernelGGL((k_convert<SI, sbf>), grid, kThreads, 0, s, in, (sbf*)out, scale, ds, n); break;
     default: set_error("unknown precision %d", pout); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
+  kt.done((double)n * (sizeof(SI) + pair_bytes(pout)), 0);
   return DW_OK;
 }
 }  // namespace
 
-dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s) {
+dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s,
+                         const double* dscale) {
   switch (pin) {
-    case DW_PREC_F64: return convert_from((const s64*)in, pout, out, scale, n, s);
-    case DW_PREC_F32: return convert_from((const s32*)in, pout, out, scale, n, s);
-    case DW_PREC_F16: return convert_from((const s16*)in, pout, out, scale, n, s);
-    case DW_PREC_BF16: return convert_from((const sbf*)in, pout, out, scale, n, s);
+    case DW_PREC_F64: return convert_from((const s64*)in, pout, out, scale, dscale, n, s);
+    case DW_PREC_F32: return convert_from((const s32*)in, pout, out, scale, dscale, n, s);
+    case DW_PREC_F16: return convert_from((const s16*)in, pout, out, scale, dscale, n, s);
+    case DW_PREC_BF16: return convert_from((const sbf*)in, pout, out, scale, dscale, n, s);
     default: set_error("unknown precision %d", pin); return DW_EINVAL;
   }
 }

@@ -149,9 +149,19 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
     }
   }
   dim3 grid((unsigned)g.nbc, (unsigned)nrhs);
+  KTimer kt(DW_K_SAP, s);
   hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
                      (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs);
   DW_CHECK_LAUNCH();
+  // algorithmic traffic per site of this colour: v, 4 links, z read (or the
+  // other colour's z cleared) and z written; flops: block residual stencil
+  // plus nmr MR steps (block stencil over the kept hops + 4 block vector ops)
+  double kept = 0;
+  for (int mu = 0; mu < 4; ++mu) kept += 2.0 * (g.B[mu] - 1) / g.B[mu];
+  const double sites = (double)g.nbc * g.bvol * nrhs;
+  const double sv = sizeof(SV), sz = sizeof(SZ), sg = sizeof(SG);
+  kt.done(sites * (12 * sv + 36 * sg + 24 * sz),
+          sites * ((z_zero ? 0.0 : 1368.0) + nmr * (48.0 + 168.0 * kept + 336.0)));
   return DW_OK;
 }
 

@@ -115,6 +115,7 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
     return DW_EINVAL;
   }
   DW_TRY(check_device(ctx));
+  ProfScope ps(ctx);
   dw_field f = new (std::nothrow) dw_field_s;
   if (!f) {
     set_error("out of host memory");
@@ -170,6 +171,7 @@ dw_status dw_apply(dw_field f, double m0, const double* x, double* y, int32_t nr
     return DW_EINVAL;
   }
   DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
   const Geom& g = f->g;
   const size_t n = (size_t)g.V * 12;
   DevBuf xi, yi;
@@ -191,6 +193,7 @@ dw_status dw_apply_ex(dw_field f, double m0, int32_t prec, const void* x, void* 
   }
   if (nrhs == 0) return DW_OK;
   DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
   return launch_dslash_lowp(f->g, m0, prec, x, f->U[prec], y, nrhs, stream);
 }
 
@@ -202,6 +205,7 @@ dw_status dw_pack(dw_field f, int32_t prec, const double* x, void* xi, int32_t n
   }
   if (nrhs == 0) return DW_OK;
   DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
   return launch_pack_spinor(f->g, prec, x, xi, 1.0, nrhs, stream);
 }
 
@@ -213,6 +217,7 @@ dw_status dw_unpack(dw_field f, int32_t prec, const void* xi, double* x, int32_t
   }
   if (nrhs == 0) return DW_OK;
   DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
   return launch_unpack_spinor(f->g, prec, xi, x, 1.0, nrhs, stream);
 }
 
@@ -264,6 +269,7 @@ extern "C" dw_status sap_precondition(dw_field f, double m0, const sap_params* s
   DW_TRY(check_sap_params(f->g, sp));
   if (nrhs == 0) return DW_OK;
   DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
   const Geom& g = f->g;
   const long long n = g.V * 12;
   const int prec = sp->storage;

@@ -11,11 +11,15 @@
 //                   result kept in Z at FP32 (FP64 for FP64 storage);
 //   w = D z_j       FP64 operator on the stored z_j, so A Z = V H^ holds to
 //                   FP64 accuracy whatever precision Z has;
-//   h = V^H w, w -= V h, twice (classical Gram-Schmidt with one full
-//                   reorthogonalisation; the paper prints modified GS,
-//                   both give the same H^ up to rounding);
-//   h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; implicit residual from the
-//                   small least-squares problem.
+//   classical Gram-Schmidt with one reorthogonalisation, delayed by one
+//                   step: the sweep that projects w (first pass) also
+//                   reorthogonalises the previous step's vector (second
+//                   pass), so V is read twice per step instead of four
+//                   times; the paper prints modified GS, all give the same
+//                   H^ up to rounding;
+//   h_{j+1,j} = ||w'||, implicit residual from the small least-squares
+//                   problem (the last column is provisional until the next
+//                   step's second pass, and is finalised at the cycle end).
 // Per cycle: eta, x += Z eta, explicit FP64 residual r = b - D x; stop, or
 // clean restart if ||r|| / ||r_implicit|| > t, or deflated restart:
 // harmonic Ritz pairs, Q_{k+1}, V <- V Q_{k+1}, Z <- Z Q_k, H^_k, and
@@ -40,7 +44,7 @@ using namespace dw;
 namespace {
 
 struct Work {
-  DevBuf V, Z, w, r, x, b, vs, partials, H, c, eta, h1, h2, nrm, Q, ritz, scal;
+  DevBuf V, Z, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal;
   double* scal_h = nullptr;
   ~Work() {
     if (scal_h) (void)hipHostFree(scal_h);
@@ -59,12 +63,12 @@ dw_status alloc_work(dw_field f, const fgmresdr_params* P, Work& W, hipStream_t 
   DW_TRY(W.x.alloc(ctx, (size_t)n * 16, s));
   DW_TRY(W.b.alloc(ctx, (size_t)n * 16, s));
   DW_TRY(W.vs.alloc(ctx, (size_t)n * pair_bytes(prec), s));
-  DW_TRY(W.partials.alloc(ctx, (size_t)kLd * kBlasGrid * 16, s));
+  DW_TRY(W.partials.alloc(ctx, (size_t)(2 * kLd + 6) * kBlasGrid * 16, s));
   DW_TRY(W.H.alloc(ctx, (size_t)kLd * kMaxM * 16, s));
   DW_TRY(W.c.alloc(ctx, (size_t)kLd * 16, s));
   DW_TRY(W.eta.alloc(ctx, (size_t)kMaxM * 16, s));
-  DW_TRY(W.h1.alloc(ctx, (size_t)kLd * 16, s));
-  DW_TRY(W.h2.alloc(ctx, (size_t)kLd * 16, s));
+  DW_TRY(W.red.alloc(ctx, (size_t)(2 * kLd + 6) * 16, s));
+  DW_TRY(W.coef.alloc(ctx, (size_t)(2 * kLd + 4) * 16, s));
   DW_TRY(W.nrm.alloc(ctx, 16, s));
   DW_TRY(W.Q.alloc(ctx, (size_t)kLd * 25 * 16, s));
   DW_TRY(W.ritz.alloc(ctx, (size_t)kMaxM * 16, s));
@@ -78,6 +82,7 @@ dw_status readback(Work& W, hipStream_t s) {
   DW_CHECK_HIP(hipMemcpyAsync(W.scal_h, W.scal.p, kSclCount * sizeof(double), hipMemcpyDeviceToHost, s));
   DW_CHECK_HIP(hipMemcpyAsync(W.scal_h + kSclCount, W.nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   DW_CHECK_HIP(hipStreamSynchronize(s));
+  prof_flush();
   return DW_OK;
 }
 
@@ -126,11 +131,16 @@ dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const doubl
     }
     int jend = j0;
     bool broke = false;
+    bool lagged = false;  // V_j holds a once-orthogonalised, unnormalised vector
+    double* red = W.red.as<double>();
+    double* coef = W.coef.as<double>();
     for (int j = j0; j < m; ++j) {
       double* vj = V + 2 * (long long)j * n;
+      double* vnext = V + 2 * (long long)(j + 1) * n;
       void* zj = Z + (size_t)j * n * zb;
-      // z_j = M v_j (SAP on sigma * v_j at storage precision)
-      DW_TRY(launch_convert(DW_PREC_F64, vj, prec, W.vs.p, sigma, n, s));
+      // z_j = M_j applied to sigma * v_j (the lagged vector scaled by its
+      // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
+      DW_TRY(launch_convert(DW_PREC_F64, vj, prec, W.vs.p, sigma, n, s, lagged ? scal + kSclHinv : nullptr));
       for (int cyc = 0; cyc < P->sap.ncycles; ++cyc)
         for (int colour = 0; colour < 2; ++colour)
           DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zj, f->U[prec], colour, P->sap.nmr,
@@ -138,21 +148,29 @@ dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const doubl
       // w = D z_j in FP64 on the stored z_j
       DW_TRY(launch_dslash_outer(g, m0, zprec, zj, 1.0 / sigma, f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, 1, n,
                                  n, s));
-      // classical Gram-Schmidt, two passes
-      DW_TRY(blas_dots(DW_PREC_F64, V, n, j + 1, W.w.as<double>(), n, partials, W.h1.as<double>(), 1, 0, s));
-      DW_TRY(blas_sub_cols(V, n, j + 1, W.h1.as<double>(), W.w.as<double>(), n, s));
-      DW_TRY(blas_dots(DW_PREC_F64, V, n, j + 1, W.w.as<double>(), n, partials, W.h2.as<double>(), 1, 0, s));
-      DW_TRY(blas_sub_cols(V, n, j + 1, W.h2.as<double>(), W.w.as<double>(), n, s));
-      DW_TRY(blas_dots(DW_PREC_F64, W.w.p, n, 1, W.w.as<double>(), n, partials, W.nrm.as<double>(), 1, 0, s));
-      DW_TRY(dense_step(W.H.as<double>(), j, W.h1.as<double>(), W.h2.as<double>(), W.nrm.as<double>(),
-                        W.c.as<double>(), scal, bd_tol, s));
-      DW_TRY(blas_scale(W.w.as<double>(), V + 2 * (long long)(j + 1) * n, scal + kSclHinv, n, s));
+      // Gram-Schmidt with delayed reorthogonalisation: one sweep of dot
+      // products finalises v_j (second pass) and projects w (first pass),
+      // one update sweep writes v_j and the next lagged vector w'.
+      const int nv = lagged ? j : j + 1;
+      DW_TRY(gs_reduce(V, n, nv, lagged ? vj : nullptr, W.w.as<double>(), n, partials, red, s));
+      DW_TRY(dense_gs_coef(W.H.as<double>(), nv, lagged ? j : -1, j, lagged ? 1 : 0, 1, red, coef, scal, bd_tol, s));
+      DW_TRY(gs_update(V, n, nv, lagged ? j : -1, W.w.as<double>(), vnext, coef, n, partials, W.nrm.as<double>(), s));
+      DW_TRY(dense_step2(W.H.as<double>(), j, W.nrm.as<double>(), W.c.as<double>(), scal, bd_tol, s));
+      lagged = true;
       ++iters;
       jend = j + 1;
       DW_TRY(readback(W, s));
       res_i = W.scal_h[kSclResImp];
       broke = W.scal_h[kSclBreak] != 0.0;
       if (broke || res_i <= P->tol * bnorm || iters >= P->max_iter) break;
+    }
+    // finalise the last lagged vector (second Gram-Schmidt pass) so that
+    // V_{jend+1} is orthonormal and H^ exact; after a breakdown it is unused
+    if (lagged && !broke) {
+      double* vl = V + 2 * (long long)jend * n;
+      DW_TRY(gs_reduce(V, n, jend, vl, nullptr, n, partials, red, s));
+      DW_TRY(dense_gs_coef(W.H.as<double>(), jend, jend, -1, 1, 0, red, coef, scal, bd_tol, s));
+      DW_TRY(gs_update(V, n, jend, jend, nullptr, nullptr, coef, n, partials, nullptr, s));
     }
     // iterate and explicit FP64 residual
     DW_TRY(dense_lsq(W.H.as<double>(), jend, W.c.as<double>(), W.eta.as<double>(), scal, s));
@@ -230,6 +248,7 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
   int cur = -1;
   DW_CHECK_HIP(hipGetDevice(&cur));
   if (cur != f->ctx->device) DW_CHECK_HIP(hipSetDevice(f->ctx->device));
+  ProfScope ps(f->ctx);
   Work W;
   DW_TRY(alloc_work(f, P, W, stream));
   const long long n = f->g.V * 12;

@@ -1,0 +1,72 @@
+"""Writes tests/golden/critical_mass.json: the leftmost eigenvalues of the
+massless Wilson-Dirac operator D(0) for the seeded synthetic gauge fields,
+from which the near-critical masses of the workloads are set.
+
+Uses only the FP64 oracle's operator (and SciPy's ARPACK). Since
+D(m0) = D(0) + m0 I exactly, the eigenvalue of D(m0) closest to the left
+edge is lambda_edge + m0; the critical mass is m_c = -Re(lambda_edge) and
+a near-critical mass is m0 = m_c + delta.
+
+Usage: python tests/golden/tune_critical_mass.py [name ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.sparse.linalg as sla
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import wilson as W  # noqa: E402
+
+OUT = os.path.join(HERE, "critical_mass.json")
+
+# name: (L, eps, gauge seed)
+FIELDS = {
+    "8^4_eps0.3": ((8, 8, 8, 8), 0.3, 0),
+    "16^3x32_eps0.6": ((16, 16, 16, 32), 0.6, 0),
+    "16^3x32_eps0.7": ((16, 16, 16, 32), 0.7, 0),
+}
+
+
+def leftmost(L, eps, seed, nev=12, ncv=64, tol=1e-9):
+    U = synth.gauge_field(L, eps, seed)
+    shp = synth.lattice_shape(L) + (4, 3)
+    n = int(np.prod(shp))
+    count = [0]
+
+    def mv(v):
+        count[0] += 1
+        return W.apply_D(U, 0.0, v.reshape(shp).astype(np.complex128)).reshape(-1)
+
+    op = sla.LinearOperator((n, n), matvec=mv, dtype=np.complex128)
+    v0 = synth.gaussian_spinor(L, 4242).reshape(-1)
+    t0 = time.time()
+    ev = sla.eigs(op, k=nev, which="SR", ncv=ncv, tol=tol, v0=v0, return_eigenvectors=False, maxiter=5000)
+    ev = ev[np.argsort(ev.real)]
+    return ev, count[0], time.time() - t0
+
+
+def main(names):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in names:
+        L, eps, seed = FIELDS[name]
+        ev, nmv, secs = leftmost(L, eps, seed)
+        data[name] = {
+            "L": list(L), "eps": eps, "seed": seed,
+            "leftmost_eigenvalues_D0": [[float(e.real), float(e.imag)] for e in ev],
+            "m_c": float(-ev[0].real),
+            "matvecs": nmv, "seconds": round(secs, 1),
+            "method": "scipy.sparse.linalg.eigs(which='SR', k=12, ncv=64, tol=1e-9) on oracle.wilson.apply_D(U, 0, .)",
+        }
+        json.dump(data, open(OUT, "w"), indent=1)
+        print(name, "m_c", -ev[0].real, "edge", ev[:4], nmv, "matvecs", round(secs), "s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(FIELDS))
