@@ -7,8 +7,10 @@
 // and blocks of one colour do not couple (Section 2, red/black colouring).
 //
 // Internal ordering (private to the library):
-//   block index b in [0, nblk): colour-major, blocks of colour 0 first,
-//     then colour 1; within a colour, lexicographic in (bt, bz, by, bx/2);
+//   block index b in [0, nblk): lexicographic in the block coordinates,
+//     b = bx + Nx*(by + Ny*(bz + Nz*bt)), so that neighbouring blocks are
+//     close in memory and in launch order; the j-th block of a colour is
+//     found by colour_block();
 //   local site index l in [0, bvol): lx + Bx*(ly + By*(lz + Bz*lt));
 //   spinor:  element (b, comp, l) at ((b*12 + comp)*bvol + l), comp = spin*3 + colour;
 //   gauge:   element (b, mu, e, l) at (((b*4 + mu)*9 + e)*bvol + l), e = a*3 + b.
@@ -63,23 +65,44 @@ inline const char* make_geom(const int L[4], const int B[4], Geom* g) {
 }
 
 __host__ __device__ __forceinline__ void decode_block(const Geom& g, int b, int bc[4]) {
-  int c = b >= g.nbc ? 1 : 0;
-  int j = b - c * g.nbc;
-  int hx = g.N[0] >> 1;
-  int q = j / hx;
-  int bx2 = j - q * hx;
+  bc[0] = b % g.N[0];
+  int q = b / g.N[0];
   bc[1] = q % g.N[1];
   q /= g.N[1];
   bc[2] = q % g.N[2];
   bc[3] = q / g.N[2];
-  bc[0] = 2 * bx2 + ((c + bc[1] + bc[2] + bc[3]) & 1);
 }
 
 __host__ __device__ __forceinline__ int encode_block(const Geom& g, const int bc[4]) {
-  int c = (bc[0] + bc[1] + bc[2] + bc[3]) & 1;
-  int j = (bc[0] >> 1) + (g.N[0] >> 1) * (bc[1] + g.N[1] * (bc[2] + g.N[2] * bc[3]));
-  return c * g.nbc + j;
+  return bc[0] + g.N[0] * (bc[1] + g.N[1] * (bc[2] + g.N[2] * bc[3]));
 }
+
+// j-th block (lexicographic order) among the blocks of `colour`, whose
+// colour is the parity of the sum of the block coordinates; N_x is even,
+// so every x-row of blocks holds N_x/2 blocks of each colour.
+__host__ __device__ __forceinline__ int colour_block(const Geom& g, int colour, int j) {
+  const int hx = g.N[0] >> 1;
+  int q = j / hx;
+  const int bx2 = j - q * hx;
+  const int by = q % g.N[1];
+  q /= g.N[1];
+  const int bz = q % g.N[2];
+  const int bt = q / g.N[2];
+  const int bx = 2 * bx2 + ((colour + by + bz + bt) & 1);
+  return bx + g.N[0] * (by + g.N[1] * (bz + g.N[2] * bt));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2. Remapping launch index i so that XCD x receives the contiguous range
+// [x*per, (x+1)*per) of work items keeps neighbouring blocks in one L2.
+// Returns -1 for launch indices past the end (the grid is rounded up).
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int xcd_remap(int i, int count) {
+  const int per = (count + kXcds - 1) / kXcds;
+  const int r = (i % kXcds) * per + i / kXcds;
+  return r < count ? r : -1;
+}
+__host__ __device__ __forceinline__ int xcd_grid(int count) { return ((count + kXcds - 1) / kXcds) * kXcds; }
 
 __host__ __device__ __forceinline__ void decode_local(const Geom& g, int l, int lc[4]) {
   lc[0] = l % g.B[0];

@@ -88,6 +88,58 @@ __device__ __forceinline__ void hop(cplx<T> acc[12], PsiF&& psi, UF&& u) {
   }
 }
 
+// The three parts of one hop, for kernels that move half spinors around.
+// proj: h = upper two spin components of (1 -/+ g_mu) psi.
+template <int MU, int DIR, typename T, typename PsiF>
+__device__ __forceinline__ void proj(PsiF&& psi, cplx<T> h0[3], cplx<T> h1[3]) {
+  using P = proj_table<MU>;
+  constexpr int A = DIR > 0 ? P::a : neg(P::a);
+  constexpr int B = DIR > 0 ? P::b : neg(P::b);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    h0[a] = psi(a) + coef<A>(psi(P::pa * 3 + a));
+    h1[a] = psi(3 + a) + coef<B>(psi(P::pb * 3 + a));
+  }
+}
+// g = W h with W = U (DAG false) or U^+ (DAG true), for both spin rows
+template <bool DAG, typename T, typename UF>
+__device__ __forceinline__ void su3_mul(UF&& u, const cplx<T> h0[3], const cplx<T> h1[3], cplx<T> g0[3],
+                                        cplx<T> g1[3]) {
+  cplx<T> w[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) w[e] = u(e);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if constexpr (!DAG) {
+        s0 += w[a * 3 + b] * h0[b];
+        s1 += w[a * 3 + b] * h1[b];
+      } else {
+        s0 += cdot(w[b * 3 + a], h0[b]);
+        s1 += cdot(w[b * 3 + a], h1[b]);
+      }
+    }
+    g0[a] = s0;
+    g1[a] = s1;
+  }
+}
+// acc += the full spinor rebuilt from the half spinor g of hop (MU, DIR)
+template <int MU, int DIR, typename T>
+__device__ __forceinline__ void recon_acc(cplx<T> acc[12], const cplx<T> g0[3], const cplx<T> g1[3]) {
+  using P = proj_table<MU>;
+  constexpr int C = DIR > 0 ? P::c : neg(P::c);
+  constexpr int D = DIR > 0 ? P::d : neg(P::d);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] += g0[a];
+    acc[3 + a] += g1[a];
+    acc[6 + a] += coef<C>(P::qc == 0 ? g0[a] : g1[a]);
+    acc[9 + a] += coef<D>(P::qd == 0 ? g0[a] : g1[a]);
+  }
+}
+
 // Dispatch hop h = 2*mu + (0: forward, 1: backward). h is uniform across the
 // wave, so the switch is a scalar branch to code with compile-time
 // projection coefficients.
@@ -148,6 +200,47 @@ __device__ __forceinline__ void hop_sum_block(const Geom& g, int b, int l, const
     const long long ub = gauge_index(g, b, mu, 0, fwd ? l : nl);
     hop_dispatch<T>(h, acc, [&](int comp) { return xin(nl, comp); },
                     [&](int e) { return ld<T>(U + ub + (long long)e * g.bvol); });
+  }
+}
+
+// Hopping sum of site (b, l) for kernels that stage a block in LDS:
+// in-block neighbours through xin_blk(nl, comp) and in-block links through
+// u_blk(mu, e, local site); with HALO, neighbours in other blocks through
+// xin_halo(nb, nl, comp) and their links through u_halo(nb, mu, e, nl)
+// (hops leaving the block are dropped without HALO, eq. 2).
+template <typename T, bool HALO, typename XB, typename UB, typename XH, typename UH>
+__device__ __forceinline__ void hop_sum_staged(const Geom& g, int b, int l, const int bc[4], const int lc[4],
+                                               XB&& xin_blk, UB&& u_blk, XH&& xin_halo, UH&& u_halo,
+                                               cplx<T> acc[12]) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+#pragma unroll 1
+  for (int h = 0; h < 8; ++h) {
+    const int mu = h >> 1;
+    const bool fwd = (h & 1) == 0;
+    const int st = g.lstride[mu];
+    const bool inb = fwd ? lc[mu] < g.B[mu] - 1 : lc[mu] > 0;
+    if (inb) {
+      const int nl = fwd ? l + st : l - st;
+      const int ul = fwd ? l : nl;
+      hop_dispatch<T>(h, acc, [&](int k) { return xin_blk(nl, k); }, [&](int e) { return u_blk(mu, e, ul); });
+    } else if constexpr (HALO) {
+      int c2[4] = {bc[0], bc[1], bc[2], bc[3]};
+      int nl;
+      if (fwd) {
+        c2[mu] = (bc[mu] + 1 == g.N[mu]) ? 0 : bc[mu] + 1;
+        nl = l - (g.B[mu] - 1) * st;
+      } else {
+        c2[mu] = (bc[mu] == 0) ? g.N[mu] - 1 : bc[mu] - 1;
+        nl = l + (g.B[mu] - 1) * st;
+      }
+      const int nb = encode_block(g, c2);
+      if (fwd)
+        hop_dispatch<T>(h, acc, [&](int k) { return xin_halo(nb, nl, k); }, [&](int e) { return u_blk(mu, e, l); });
+      else
+        hop_dispatch<T>(h, acc, [&](int k) { return xin_halo(nb, nl, k); },
+                        [&](int e) { return u_halo(nb, mu, e, nl); });
+    }
   }
 }
 

@@ -1,11 +1,15 @@
 // Wilson-Dirac operator on the whole periodic lattice (paper eq. 1).
 //
-// One thread per site; every thread gathers its 8 neighbours' spinors and
-// the 8 links it needs (its own 4 forward links and the 4 backward links
-// stored at the neighbours). Fields are in the block-tiled internal layout,
-// so each spinor component and link entry is a contiguous run over a
-// block's sites and a wavefront's loads are coalesced; neighbour reuse
-// across threads goes through L1/L2.
+// One workgroup per storage block, one thread per site. The block's
+// spinor is staged in LDS once, so in-block neighbours are read from LDS;
+// only the faces of neighbouring blocks come from L2/HBM. Every link is read
+// once: a thread loads its own forward link U_mu(n), uses it for the
+// forward hop and also forms U_mu(n)^+ (1 + g_mu) psi(n), the backward-hop
+// half spinor that site n + mu needs, and hands it over through LDS
+// (sites on a block's lower face compute theirs from the neighbouring
+// block). Launch order is XCD-aware so neighbouring blocks share an L2.
+// Blocks whose LDS footprint exceeds the CU's 160 KiB fall back to a
+// gather kernel that reads all neighbours through the caches.
 //
 // Bandwidth bound: per site and right-hand side the algorithmic traffic is
 // one spinor read, 4 links read and one spinor write (FP64: 960 bytes).
@@ -21,12 +25,135 @@ constexpr int kThreads = 256;
 // + 24 accumulation) - 24 (first accumulation is a copy) + 48 (diagonal)
 constexpr double kFlopsPerSite = 1368.0;
 
+// ---- block-staged kernel ---------------------------------------------------------
+template <typename T, typename SX, typename SG>
+struct BlkCtx {
+  const Geom& g;
+  int b, l;
+  bool active;
+  const int* bc;
+  const int* lc;
+  const SX* xr;
+  const SX* xsh;   // LDS: block spinor [12][bvol], storage type
+  cplx<T>* pb;     // LDS: handed-over half spinors [6][bvol]
+  const SG* U;
+};
+
+template <int MU, typename T, typename SX, typename SG>
+__device__ __forceinline__ void blk_dir(const BlkCtx<T, SX, SG>& c, cplx<T> acc[12], const cplx<T> psi[12]) {
+  const Geom& g = c.g;
+  const int bvol = g.bvol, l = c.l;
+  const int st = g.lstride[MU];
+  cplx<T> h0[3], h1[3], g0[3], g1[3];
+  if (c.active) {
+    cplx<T> w[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[e] = ld<T>(c.U + gauge_index(g, c.b, MU, e, l));
+    auto wl = [&](int e) { return w[e]; };
+    // backward-hop half spinor for site n + mu: U_mu(n)^+ (1 + g_mu) psi(n)
+    proj<MU, -1, T>([&](int k) { return psi[k]; }, h0, h1);
+    su3_mul<true, T>(wl, h0, h1, g0, g1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c.pb[a * bvol + l] = g0[a];
+      c.pb[(3 + a) * bvol + l] = g1[a];
+    }
+    // forward hop: (1 - g_mu) U_mu(n) psi(n + mu)
+    if (c.lc[MU] < g.B[MU] - 1) {
+      proj<MU, +1, T>([&](int k) { return ld<T>(c.xsh + k * bvol + l + st); }, h0, h1);
+    } else {
+      int c2[4] = {c.bc[0], c.bc[1], c.bc[2], c.bc[3]};
+      c2[MU] = (c.bc[MU] + 1 == g.N[MU]) ? 0 : c.bc[MU] + 1;
+      const int nb = encode_block(g, c2), nl = l - (g.B[MU] - 1) * st;
+      proj<MU, +1, T>([&](int k) { return ld<T>(c.xr + spinor_index(g, nb, k, nl)); }, h0, h1);
+    }
+    su3_mul<false, T>(wl, h0, h1, g0, g1);
+    recon_acc<MU, +1, T>(acc, g0, g1);
+  }
+  __syncthreads();
+  if (c.active) {
+    if (c.lc[MU] > 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        g0[a] = c.pb[a * bvol + l - st];
+        g1[a] = c.pb[(3 + a) * bvol + l - st];
+      }
+    } else {
+      int c2[4] = {c.bc[0], c.bc[1], c.bc[2], c.bc[3]};
+      c2[MU] = (c.bc[MU] == 0) ? g.N[MU] - 1 : c.bc[MU] - 1;
+      const int nb = encode_block(g, c2), nl = l + (g.B[MU] - 1) * st;
+      proj<MU, -1, T>([&](int k) { return ld<T>(c.xr + spinor_index(g, nb, k, nl)); }, h0, h1);
+      su3_mul<true, T>([&](int e) { return ld<T>(c.U + gauge_index(g, nb, MU, e, nl)); }, h0, h1, g0, g1);
+    }
+    recon_acc<MU, -1, T>(acc, g0, g1);
+  }
+  __syncthreads();
+}
+
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+template <typename T, typename SX, typename SG, typename SY, int MODE, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+    k_dslash_blk(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
+                 const SY* __restrict__ bsrc, long long xs, long long ys) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  SX* xsh = reinterpret_cast<SX*>(smem);
+  cplx<T>* pb = reinterpret_cast<cplx<T>*>(smem + align16((size_t)12 * g.bvol * sizeof(SX)));
+  const int b = xcd_remap(blockIdx.x, g.nblk);
+  if (b < 0) return;  // uniform for the workgroup
+  const int l = threadIdx.x;
+  const bool active = l < g.bvol;
+  const SX* xr = x + (long long)blockIdx.y * xs;
+  SY* yr = y + (long long)blockIdx.y * ys;
+  int bc[4], lc[4] = {0, 0, 0, 0};
+  decode_block(g, b, bc);
+  cplx<T> psi[12], acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    psi[k] = mk<T>(0, 0);
+    acc[k] = mk<T>(0, 0);
+  }
+  if (active) {
+    decode_local(g, l, lc);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const SX v = xr[spinor_index(g, b, k, l)];
+      xsh[k * g.bvol + l] = v;
+      psi[k] = storage_traits<SX>::template load<T>(v);
+    }
+  }
+  __syncthreads();
+  const BlkCtx<T, SX, SG> c{g, b, l, active, bc, lc, xr, xsh, pb, U};
+  blk_dir<0>(c, acc, psi);
+  blk_dir<1>(c, acc, psi);
+  blk_dir<2>(c, acc, psi);
+  blk_dir<3>(c, acc, psi);
+  if (active) {
+    const T half = (T)0.5;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const long long idx = spinor_index(g, b, k, l);
+      cplx<T> d = scale * (diag * psi[k] - half * acc[k]);
+      if constexpr (MODE == 1) d = ld<T>(bsrc + (long long)blockIdx.y * ys + idx) - d;
+      st(yr + idx, d);
+    }
+  }
+}
+
+template <typename T, typename SX>
+size_t blk_lds(const Geom& g) {
+  return align16((size_t)12 * g.bvol * sizeof(SX)) + (size_t)6 * g.bvol * sizeof(cplx<T>);
+}
+
+// ---- gather kernel (blocks too large for LDS staging) -------------------------------
 // MODE 0: y = scale * D x ; MODE 1: y = b - scale * D x
 template <typename T, typename SX, typename SG, typename SY, int MODE>
 __global__ void __launch_bounds__(kThreads)
     k_dslash(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
              const SY* __restrict__ bsrc, long long xs, long long ys) {
-  const long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const int chunk = xcd_remap(blockIdx.x, (int)((g.V + kThreads - 1) / kThreads));
+  if (chunk < 0) return;
+  const long long s = (long long)chunk * kThreads + threadIdx.x;
   if (s >= g.V) return;
   const SX* xr = x + (long long)blockIdx.y * xs;
   SY* yr = y + (long long)blockIdx.y * ys;
@@ -52,7 +179,42 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-dim3 grid_for(const Geom& g, int nrhs) { return dim3((unsigned)((g.V + kThreads - 1) / kThreads), (unsigned)nrhs); }
+template <typename T, typename SX, typename SG, typename SY, int MODE>
+dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
+                     long long ys, int nrhs, hipStream_t s);
+
+dim3 grid_for(const Geom& g, int nrhs) {
+  return dim3((unsigned)xcd_grid((int)((g.V + kThreads - 1) / kThreads)), (unsigned)nrhs);
+}
+
+template <typename T, typename SX, typename SG, typename SY, int MODE>
+dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
+                     long long ys, int nrhs, hipStream_t s) {
+  const size_t lds = blk_lds<T, SX>(g);
+  const int threads = ((g.bvol + 63) / 64) * 64;
+  if (lds <= 160 * 1024) {
+    auto launch_t = [&](auto kernel) -> dw_status {
+      if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+          set_error("hipFuncSetAttribute(LDS %zu) failed: %s", lds, hipGetErrorString(e));
+          return DW_EHIP;
+        }
+      }
+      dim3 grid((unsigned)xcd_grid(g.nblk), (unsigned)nrhs);
+      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys);
+      DW_CHECK_LAUNCH();
+      return DW_OK;
+    };
+    if (threads <= 256) return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 256>);
+    if (threads <= 512) return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 512>);
+    return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 1024>);
+  }
+  hipLaunchKernelGGL((k_dslash<T, SX, SG, SY, MODE>), grid_for(g, nrhs), kThreads, 0, s, g, diag, x, scale, U, y, b,
+                     xs, ys);
+  DW_CHECK_LAUNCH();
+  return DW_OK;
+}
 
 }  // namespace
 
@@ -63,25 +225,21 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
   const s64* Ug = (const s64*)U64;
   s64* yo = (s64*)y;
   const s64* bo = (const s64*)b;
-  dim3 grid = grid_for(g, nrhs);
   KTimer kt(DW_K_DSLASH_F64, s);
+  dw_status st;
   if (prec_x == DW_PREC_F64) {
     const s64* xi = (const s64*)x;
-    if (mode == 0)
-      hipLaunchKernelGGL((k_dslash<double, s64, s64, s64, 0>), grid, kThreads, 0, s, g, diag, xi, scale, Ug, yo, bo, xs, ys);
-    else
-      hipLaunchKernelGGL((k_dslash<double, s64, s64, s64, 1>), grid, kThreads, 0, s, g, diag, xi, scale, Ug, yo, bo, xs, ys);
+    st = mode == 0 ? launch_any<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s)
+                   : launch_any<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s);
   } else if (prec_x == DW_PREC_F32) {
     const s32* xi = (const s32*)x;
-    if (mode == 0)
-      hipLaunchKernelGGL((k_dslash<double, s32, s64, s64, 0>), grid, kThreads, 0, s, g, diag, xi, scale, Ug, yo, bo, xs, ys);
-    else
-      hipLaunchKernelGGL((k_dslash<double, s32, s64, s64, 1>), grid, kThreads, 0, s, g, diag, xi, scale, Ug, yo, bo, xs, ys);
+    st = mode == 0 ? launch_any<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s)
+                   : launch_any<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s);
   } else {
     set_error("outer dslash input precision must be F64 or F32");
     return DW_EINVAL;
   }
-  DW_CHECK_LAUNCH();
+  DW_TRY(st);
   kt.done((double)g.V * nrhs * (12.0 * pair_bytes(prec_x) + 36 * 16 + 12 * 16 + (mode == 1 ? 12 * 16 : 0)),
           (double)g.V * nrhs * kFlopsPerSite);
   return DW_OK;
@@ -89,29 +247,30 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
 
 dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
                              hipStream_t s) {
-  dim3 grid = grid_for(g, nrhs);
-  const long long st = g.V * 12;
+  const long long sd = g.V * 12;
   KTimer kt(DW_K_DSLASH_LOWP, s);
+  dw_status st;
+  const float df = (float)(4.0 + m0);
   switch (prec) {
     case DW_PREC_F64:
-      hipLaunchKernelGGL((k_dslash<double, s64, s64, s64, 0>), grid, kThreads, 0, s, g, 4.0 + m0, (const s64*)x, 1.0,
-                         (const s64*)U, (s64*)y, (const s64*)nullptr, st, st);
+      st = launch_any<double, s64, s64, s64, 0>(g, 4.0 + m0, (const s64*)x, 1.0, (const s64*)U, (s64*)y, nullptr, sd,
+                                                sd, nrhs, s);
       break;
     case DW_PREC_F32:
-      hipLaunchKernelGGL((k_dslash<float, s32, s32, s32, 0>), grid, kThreads, 0, s, g, (float)(4.0 + m0),
-                         (const s32*)x, 1.0f, (const s32*)U, (s32*)y, (const s32*)nullptr, st, st);
+      st = launch_any<float, s32, s32, s32, 0>(g, df, (const s32*)x, 1.0f, (const s32*)U, (s32*)y, nullptr, sd, sd,
+                                               nrhs, s);
       break;
     case DW_PREC_F16:
-      hipLaunchKernelGGL((k_dslash<float, s16, s16, s16, 0>), grid, kThreads, 0, s, g, (float)(4.0 + m0),
-                         (const s16*)x, 1.0f, (const s16*)U, (s16*)y, (const s16*)nullptr, st, st);
+      st = launch_any<float, s16, s16, s16, 0>(g, df, (const s16*)x, 1.0f, (const s16*)U, (s16*)y, nullptr, sd, sd,
+                                               nrhs, s);
       break;
     case DW_PREC_BF16:
-      hipLaunchKernelGGL((k_dslash<float, sbf, sbf, sbf, 0>), grid, kThreads, 0, s, g, (float)(4.0 + m0),
-                         (const sbf*)x, 1.0f, (const sbf*)U, (sbf*)y, (const sbf*)nullptr, st, st);
+      st = launch_any<float, sbf, sbf, sbf, 0>(g, df, (const sbf*)x, 1.0f, (const sbf*)U, (sbf*)y, nullptr, sd, sd,
+                                               nrhs, s);
       break;
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
-  DW_CHECK_LAUNCH();
+  DW_TRY(st);
   kt.done((double)g.V * nrhs * 60.0 * pair_bytes(prec), (double)g.V * nrhs * kFlopsPerSite);
   return DW_OK;
 }

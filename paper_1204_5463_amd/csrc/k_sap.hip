@@ -7,7 +7,9 @@
 //      block and its one-site halo in blocks of the other colour;
 //   2. nmr minimal-residual steps on D^l y = r (eq. 2) starting from y = 0,
 //      alpha = (p^H rho) / (p^H p) over the block's sites, with the
-//      residual rho kept in LDS so that neighbours can read it;
+//      residual rho kept in LDS so that neighbours can read it and, when
+//      they fit (FP32/FP16/BF16 storage), the block's links staged in LDS
+//      once so the MR steps touch no global memory;
 //   3. z += y on the block.
 // With z_zero set (first colour of the first cycle) z is not read and is
 // initialised here: y on this colour's blocks, zero on the other colour's.
@@ -31,25 +33,42 @@ __device__ __forceinline__ T wave_sum(T a) {
   return a;
 }
 
-template <typename T, typename SV, typename SZ, typename SG, int MAXT>
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL>
 __global__ void __launch_bounds__(MAXT)
     k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
                  int nmr, int z_zero, long long vs, long long zs) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem);
+  // LDS: [links 36 x bvol (LDSL)] [rho 12 x bvol] [reduction 2 x nw x 3]
+  SG* lks = reinterpret_cast<SG*>(smem);
+  const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
+  cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem + lbytes);
   const int nw = blockDim.x / kWave;
-  T* red = reinterpret_cast<T*>(rho_s + 12 * g.bvol);  // 2 buffers x nw x 3
+  T* red = reinterpret_cast<T*>(rho_s + 12 * g.bvol);
+  const int jb = xcd_remap(blockIdx.x, g.nbc);
+  if (jb < 0) return;  // whole workgroup: uniform exit before any barrier
+  const int b = colour_block(g, colour, jb);
   const int l = threadIdx.x;
   const bool active = l < g.bvol;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const int b = colour * g.nbc + blockIdx.x;
   const SV* vr = v + (long long)blockIdx.y * vs;
   SZ* zr = z + (long long)blockIdx.y * zs;
   const T half = (T)0.5;
 
   int bc[4], lc[4] = {0, 0, 0, 0};
   decode_block(g, b, bc);
+  if (active) decode_local(g, l, lc);
+  // the block's links, read once per launch
+  if constexpr (LDSL) {
+    if (active)
+      for (int q = 0; q < 36; ++q) lks[q * g.bvol + l] = U[gauge_index(g, b, q / 9, q % 9, l)];
+  }
+  auto u_blk = [&](int mu, int e, int ls) {
+    if constexpr (LDSL) return ld<T>(lks + (mu * 9 + e) * g.bvol + ls);
+    else return ld<T>(U + gauge_index(g, b, mu, e, ls));
+  };
+  auto u_halo = [&](int nb, int mu, int e, int nl) { return ld<T>(U + gauge_index(g, nb, mu, e, nl)); };
+
   cplx<T> rho[12], y[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
@@ -57,16 +76,32 @@ __global__ void __launch_bounds__(MAXT)
     y[c] = mk<T>(0, 0);
   }
   if (active) {
-    decode_local(g, l, lc);
 #pragma unroll
     for (int c = 0; c < 12; ++c) rho[c] = ld<T>(vr + spinor_index(g, b, c, l));
-    if (!z_zero) {
-      cplx<T> acc[12];
-      hop_sum_lattice<T>(g, b, l, bc, lc, U,
-                         [&](int nb, int nl, int comp) { return ld<T>(zr + spinor_index(g, nb, comp, nl)); }, acc);
+  }
+  if (!z_zero) {
+    // block residual r = v - D z: z of this block staged in LDS, the one-site
+    // halo of z read from the neighbouring blocks of the other colour
+    cplx<T> zo[12];
+    if (active) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) rho[c] = rho[c] - diag * ld<T>(zr + spinor_index(g, b, c, l)) + half * acc[c];
+      for (int c = 0; c < 12; ++c) {
+        zo[c] = ld<T>(zr + spinor_index(g, b, c, l));
+        rho_s[c * g.bvol + l] = zo[c];
+      }
     }
+    __syncthreads();
+    if (active) {
+      cplx<T> acc[12];
+      hop_sum_staged<T, true>(
+          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * g.bvol + nl]; }, u_blk,
+          [&](int nb, int nl, int k) { return ld<T>(zr + spinor_index(g, nb, k, nl)); }, u_halo, acc);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rho[c] = rho[c] - diag * zo[c] + half * acc[c];
+    }
+    __syncthreads();  // z reads from LDS done before rho overwrites it
+  } else if constexpr (LDSL) {
+    __syncthreads();  // staged links visible
   }
 
   for (int it = 0; it < nmr; ++it) {
@@ -78,7 +113,9 @@ __global__ void __launch_bounds__(MAXT)
     cplx<T> p[12];
     T nre = 0, nim = 0, den = 0;
     if (active) {
-      hop_sum_block<T>(g, b, l, lc, U, [&](int nl, int comp) { return rho_s[comp * g.bvol + nl]; }, p);
+      hop_sum_staged<T, false>(
+          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * g.bvol + nl]; }, u_blk,
+          [&](int, int, int) { return mk<T>(0, 0); }, u_halo, p);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         p[c] = diag * rho[c] - half * p[c];
@@ -114,7 +151,6 @@ __global__ void __launch_bounds__(MAXT)
       rho[c] -= alpha * p[c];
     }
   }
-  __syncthreads();  // every thread has read z on this block before it is updated
   if (active) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -124,33 +160,35 @@ __global__ void __launch_bounds__(MAXT)
     // z starts at zero: this workgroup also clears one block of the other
     // colour (same count per colour), which this launch never reads
     if (z_zero) {
-      const int bo = (1 - colour) * g.nbc + blockIdx.x;
+      const int bo = colour_block(g, 1 - colour, jb);
 #pragma unroll
       for (int c = 0; c < 12; ++c) st(zr + spinor_index(g, bo, c, l), mk<T>(0, 0));
     }
   }
 }
 
-template <typename T, typename SV, typename SZ, typename SG, int MAXT>
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL>
 dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                 int nrhs, long long vs, long long zs, hipStream_t s) {
+                   int nrhs, long long vs, long long zs, hipStream_t s) {
   const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
-  const size_t shmem = (size_t)12 * g.bvol * sizeof(cplx<T>) + (size_t)2 * 3 * (threads / kWave) * sizeof(T);
+  const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
+  const size_t shmem =
+      lbytes + (size_t)12 * g.bvol * sizeof(cplx<T>) + (size_t)2 * 3 * (threads / kWave) * sizeof(T);
   if (shmem > 160 * 1024) {
     set_error("SAP block of %d sites needs %zu bytes of LDS", g.bvol, shmem);
     return DW_EINVAL;
   }
   if (shmem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT, LDSL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) {
       set_error("hipFuncSetAttribute(LDS %zu bytes) failed: %s", shmem, hipGetErrorString(e));
       return DW_EHIP;
     }
   }
-  dim3 grid((unsigned)g.nbc, (unsigned)nrhs);
+  dim3 grid((unsigned)xcd_grid(g.nbc), (unsigned)nrhs);
   KTimer kt(DW_K_SAP, s);
-  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
+  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
                      (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs);
   DW_CHECK_LAUNCH();
   // algorithmic traffic per site of this colour: v, 4 links, z read (or the
@@ -165,12 +203,25 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
   return DW_OK;
 }
 
+template <typename T, typename SV, typename SZ, typename SG, int MAXT>
+dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
+                   int nrhs, long long vs, long long zs, hipStream_t s) {
+  // Stage the block's links in LDS only when that keeps several workgroups
+  // per CU: the MR steps are VALU bound and lose more to lower occupancy
+  // than they gain from fewer cached link reads (measured on 4^4 blocks
+  // with FP16 links: 380 us with links from L1/L2, 517 us staged).
+  const size_t need = (size_t)36 * g.bvol * sizeof(SG) + (size_t)12 * g.bvol * sizeof(cplx<T>) + 512;
+  if (need <= 40 * 1024)
+    return launch_t<T, SV, SZ, SG, MAXT, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+  return launch_t<T, SV, SZ, SG, MAXT, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+}
+
 template <typename T, typename SV, typename SZ, typename SG>
 dw_status launch(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
                  int nrhs, long long vs, long long zs, hipStream_t s) {
-  if (g.bvol <= 256) return launch_t<T, SV, SZ, SG, 256>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-  if (g.bvol <= 512) return launch_t<T, SV, SZ, SG, 512>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-  return launch_t<T, SV, SZ, SG, 1024>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+  if (g.bvol <= 256) return launch_m<T, SV, SZ, SG, 256>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+  if (g.bvol <= 512) return launch_m<T, SV, SZ, SG, 512>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+  return launch_m<T, SV, SZ, SG, 1024>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
 }
 
 }  // namespace

@@ -7,8 +7,12 @@
 //
 // Per Arnoldi step j (flexible, Alg. 3):
 //   z_j = M_j v_j   SAP at storage precision on sigma * v_j (sigma = sqrt(n)
-//                   gives unit RMS entries; M is scale-equivariant), the
-//                   result kept in Z at FP32 (FP64 for FP64 storage);
+//                   gives unit RMS entries; M is scale-equivariant) with an
+//                   FP32 accumulator (FP64 for FP64 storage); the result is
+//                   kept in Z at FP64, which holds it exactly, so that the
+//                   rotated deflation basis Z_k = Z Q_k keeps A Z = V H^ to
+//                   FP64 accuracy (an FP32 Z_k makes the implicit residual
+//                   drift from the explicit one near convergence);
 //   w = D z_j       FP64 operator on the stored z_j, so A Z = V H^ holds to
 //                   FP64 accuracy whatever precision Z has;
 //   classical Gram-Schmidt with one reorthogonalisation, delayed by one
@@ -44,7 +48,7 @@ using namespace dw;
 namespace {
 
 struct Work {
-  DevBuf V, Z, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal;
+  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal;
   double* scal_h = nullptr;
   ~Work() {
     if (scal_h) (void)hipHostFree(scal_h);
@@ -57,7 +61,8 @@ dw_status alloc_work(dw_field f, const fgmresdr_params* P, Work& W, hipStream_t 
   const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
   dw_ctx ctx = f->ctx;
   DW_TRY(W.V.alloc(ctx, (size_t)(P->m + 1) * n * 16, s));
-  DW_TRY(W.Z.alloc(ctx, (size_t)P->m * n * pair_bytes(zprec), s));
+  DW_TRY(W.Z.alloc(ctx, (size_t)P->m * n * 16, s));
+  if (zprec != DW_PREC_F64) DW_TRY(W.zs.alloc(ctx, (size_t)n * pair_bytes(zprec), s));
   DW_TRY(W.w.alloc(ctx, (size_t)n * 16, s));
   DW_TRY(W.r.alloc(ctx, (size_t)n * 16, s));
   DW_TRY(W.x.alloc(ctx, (size_t)n * 16, s));
@@ -92,8 +97,8 @@ dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const doubl
   const long long n = g.V * 12;
   const int m = P->m, k = P->k;
   const int prec = P->sap.storage;
-  const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
-  const size_t zb = pair_bytes(zprec);
+  const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;  // SAP accumulator
+  const size_t zb = 16;                                                  // Z is FP64
   const double sigma = prec == DW_PREC_F64 ? 1.0 : sqrt((double)n);
   const double bd_tol = 1e-14;
   double* V = W.V.as<double>();
@@ -137,16 +142,18 @@ dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const doubl
     for (int j = j0; j < m; ++j) {
       double* vj = V + 2 * (long long)j * n;
       double* vnext = V + 2 * (long long)(j + 1) * n;
-      void* zj = Z + (size_t)j * n * zb;
+      double* zj = (double*)(Z + (size_t)j * n * zb);
+      void* zacc = zprec == DW_PREC_F64 ? (void*)zj : W.zs.p;
       // z_j = M_j applied to sigma * v_j (the lagged vector scaled by its
       // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
       DW_TRY(launch_convert(DW_PREC_F64, vj, prec, W.vs.p, sigma, n, s, lagged ? scal + kSclHinv : nullptr));
       for (int cyc = 0; cyc < P->sap.ncycles; ++cyc)
         for (int colour = 0; colour < 2; ++colour)
-          DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zj, f->U[prec], colour, P->sap.nmr,
+          DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
                                    cyc == 0 && colour == 0 ? 1 : 0, 1, n, n, s));
+      if (zprec != DW_PREC_F64) DW_TRY(launch_convert(zprec, zacc, DW_PREC_F64, zj, 1.0 / sigma, n, s));
       // w = D z_j in FP64 on the stored z_j
-      DW_TRY(launch_dslash_outer(g, m0, zprec, zj, 1.0 / sigma, f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, 1, n,
+      DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, zj, 1.0, f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, 1, n,
                                  n, s));
       // Gram-Schmidt with delayed reorthogonalisation: one sweep of dot
       // products finalises v_j (second pass) and projects w (first pass),
@@ -174,7 +181,7 @@ dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const doubl
     }
     // iterate and explicit FP64 residual
     DW_TRY(dense_lsq(W.H.as<double>(), jend, W.c.as<double>(), W.eta.as<double>(), scal, s));
-    DW_TRY(blas_combine(zprec, Z, n, jend, W.eta.as<double>(), 1.0 / sigma, W.x.as<double>(), n, s));
+    DW_TRY(blas_combine(DW_PREC_F64, Z, n, jend, W.eta.as<double>(), 1.0, W.x.as<double>(), n, s));
     DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.x.p, 1.0, f->U[DW_PREC_F64], W.r.as<double>(),
                                W.b.as<double>(), 1, 1, n, n, s));
     DW_TRY(blas_dots(DW_PREC_F64, W.r.p, n, 1, W.r.as<double>(), n, partials, W.nrm.as<double>(), 1, 0, s));
@@ -205,7 +212,7 @@ dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const doubl
       continue;
     }
     DW_TRY(blas_rotate(DW_PREC_F64, V, n, jend + 1, W.Q.as<double>(), kLd, k + 1, n, s));
-    DW_TRY(blas_rotate(zprec, Z, n, jend, W.Q.as<double>(), kLd, k, n, s));
+    DW_TRY(blas_rotate(DW_PREC_F64, Z, n, jend, W.Q.as<double>(), kLd, k, n, s));
     DW_CHECK_HIP(hipMemsetAsync(W.c.p, 0, (size_t)kLd * 16, s));
     DW_TRY(blas_dots(DW_PREC_F64, V, n, k + 1, W.r.as<double>(), n, partials, W.c.as<double>(), 1, 0, s));
     fresh = false;

@@ -29,6 +29,10 @@ OUT = os.path.join(HERE, "critical_mass.json")
 # name: (L, eps, gauge seed)
 FIELDS = {
     "8^4_eps0.3": ((8, 8, 8, 8), 0.3, 0),
+    "8^4_eps0.7": ((8, 8, 8, 8), 0.7, 0),
+    "12^4_eps0.7": ((12, 12, 12, 12), 0.7, 0),
+    "8^4_eps0.6": ((8, 8, 8, 8), 0.6, 0),
+    "12^4_eps0.6": ((12, 12, 12, 12), 0.6, 0),
     "16^3x32_eps0.6": ((16, 16, 16, 32), 0.6, 0),
     "16^3x32_eps0.7": ((16, 16, 16, 32), 0.7, 0),
 }
@@ -53,10 +57,10 @@ def leftmost(L, eps, seed, nev=12, ncv=64, tol=1e-9):
 
 
 def main(names):
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         L, eps, seed = FIELDS[name]
         ev, nmv, secs = leftmost(L, eps, seed)
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         data[name] = {
             "L": list(L), "eps": eps, "seed": seed,
             "leftmost_eigenvalues_D0": [[float(e.real), float(e.imag)] for e in ev],
