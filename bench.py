@@ -32,9 +32,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
     # name: lattice, eps, gauge seed, mass spec, SAP, solver
-    "32^3x64": dict(L=(32, 32, 32, 64), eps=0.7, seed=0, mass=("16^3x32_eps0.7", 0.02),
+    "32^3x64": dict(L=(32, 32, 32, 64), eps=0.7, seed=0, mass=(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
                     block=(4, 4, 4, 4), ncycles=2, nmr=5, storage="f16", m=30, k=12),
-    "16^3x32": dict(L=(16, 16, 16, 32), eps=0.6, seed=0, mass=("16^3x32_eps0.6", 0.001),
+    "16^3x32": dict(L=(16, 16, 16, 32), eps=0.6, seed=0, mass=(("16^3x32_eps0.6", "12^4_eps0.6"), 0.001),
                     block=(4, 4, 4, 4), ncycles=2, nmr=5, storage="f32", m=30, k=10),
     "8^4": dict(L=(8, 8, 8, 8), eps=0.3, seed=0, mass=(None, -0.1),
                 block=(4, 4, 4, 4), ncycles=1, nmr=4, storage="f16", m=20, k=5),
@@ -46,13 +46,45 @@ def log(*a):
 
 
 def mass_for(spec):
-    """m0 = m_c + delta, m_c from the oracle's leftmost eigenvalue of D(0)."""
-    name, delta = spec
-    if name is None:
-        return delta
+    """m0 = m_c + delta with m_c = -Re(leftmost eigenvalue of D(0)), computed
+    by the oracle for the largest lattice of the same link distribution that
+    has been tuned (tests/golden/critical_mass.json). Returns (m0, source)."""
+    names, delta = spec
+    if names is None:
+        return delta, "fixed"
     with open(os.path.join(ROOT, "tests", "golden", "critical_mass.json")) as f:
         data = json.load(f)
-    return data[name]["m_c"] + delta
+    for name in names:
+        if name in data:
+            return data[name]["m_c"] + delta, f"m_c({name}) + {delta}"
+    raise KeyError(f"no critical mass for {names}")
+
+
+def source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for fn in files:
+        with open(os.path.join(ROOT, "paper_1204_5463_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the kernel class `key` (class/workload/storage)
+    from the committed counter summary (two rocprofv3 --pmc passes,
+    FETCH_SIZE then WRITE_SIZE, scaled by what the counters read for a plain
+    copy), or None if absent or if the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        prof = json.load(f)
+    ent = prof.get("kernels", {}).get(key)
+    if not ent:
+        return None
+    if ent.get("source_sha") != source_sha(ent.get("sources", [])):
+        return None
+    return ent["bytes_per_launch"]
 
 
 def time_dslash(P, torch, f, m0, prec, reps=50, warm=10):
@@ -163,7 +195,10 @@ def main():
 
     wl = WORKLOADS[args.workload]
     L = wl["L"]
-    m0 = mass_for(wl["mass"]) if args.m0 is None else args.m0
+    if args.m0 is None:
+        m0, mass_src = mass_for(wl["mass"])
+    else:
+        m0, mass_src = args.m0, "command line"
     prec = P.PREC_NAMES[wl["storage"]]
     log(f"[bench] workload {args.workload}: L={L} eps={wl['eps']} m0={m0:.6f}; generating inputs")
     t0 = time.time()
@@ -218,8 +253,10 @@ def main():
         achieved = kd["bytes"] / kd["ms"] / 1e6
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    roofline["traffic"] = measured_traffic(f"{dom}/{args.workload}/{wl['storage']}")
     roofline.update({"kernel_class": dom, "avg_launch_ms": round(avg_ms, 4), "launches": kd["launches"],
-                     "bytes_per_launch": kd["bytes"] / max(1, kd["launches"])})
+                     "algorithmic_bytes_per_launch": kd["bytes"] / max(1, kd["launches"]),
+                     "algorithmic_flops_per_launch": kd["flops"] / max(1, kd["launches"])})
     kernels = {}
     for k, v in kern.items():
         if v["launches"] == 0:
@@ -282,7 +319,8 @@ def main():
                                f"near-critical, Gaussian RHS, SAP {wl['storage']} storage "
                                f"{'x'.join(map(str, wl['block']))} blocks s={wl['ncycles']} nMR={wl['nmr']}, "
                                f"FGMRES-DR({wl['m']},{wl['k']}) FP64 outer, tol 1e-10",
-                   "lattice": list(L), "m0": m0, "sap_storage": wl["storage"], "parallelism": "single GPU"},
+                   "lattice": list(L), "m0": m0, "m0_from": mass_src, "sap_storage": wl["storage"],
+                   "parallelism": "single GPU"},
         "iterations": st0.iterations,
         "cycles": st0.cycles,
         "clean_restarts": st0.clean_restarts,
