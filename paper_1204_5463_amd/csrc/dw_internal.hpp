@@ -142,9 +142,10 @@ dw_status launch_convert(int pin, const void* in, int pout, void* out, double sc
 // y = scale * D x (mode 0) or y = b - scale * D x (mode 1), internal layout.
 // prec_x: DW_PREC_F64 or DW_PREC_F32 input with FP64 links/output/arithmetic
 // when outer = true; otherwise everything at precision prec_x (FP32 math).
+// rlist (device, may be null): the nrhs right-hand-side indices to process.
 dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
                               double* y, const double* b, int mode, int nrhs, long long x_rhs_stride,
-                              long long y_rhs_stride, hipStream_t s);
+                              long long y_rhs_stride, hipStream_t s, const int* rlist = nullptr);
 dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
                              hipStream_t s);
 
@@ -153,6 +154,6 @@ dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, 
 // z at FP64 (prec F64) or FP32 (otherwise). z_zero: z is zero on entry.
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
                             int nmr, int z_zero, int nrhs, long long v_rhs_stride, long long z_rhs_stride,
-                            hipStream_t s);
+                            hipStream_t s, const int* rlist = nullptr);
 
 }  // namespace dw

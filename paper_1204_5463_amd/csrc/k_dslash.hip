@@ -95,16 +95,20 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(siz
 template <typename T, typename SX, typename SG, typename SY, int MODE, int MAXT>
 __global__ void __launch_bounds__(MAXT)
     k_dslash_blk(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
-                 const SY* __restrict__ bsrc, long long xs, long long ys) {
+                 const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   SX* xsh = reinterpret_cast<SX*>(smem);
   cplx<T>* pb = reinterpret_cast<cplx<T>*>(smem + align16((size_t)12 * g.bvol * sizeof(SX)));
-  const int b = xcd_remap(blockIdx.x, g.nblk);
-  if (b < 0) return;  // uniform for the workgroup
+  // work item -> (block, RHS) with the RHS fastest: workgroups that read the
+  // same links run together on one XCD
+  const int wi = xcd_remap(blockIdx.x, g.nblk * nr);
+  if (wi < 0) return;  // uniform for the workgroup
+  const int b = wi / nr;
+  const int rhs = rlist ? rlist[wi - b * nr] : wi - b * nr;
   const int l = threadIdx.x;
   const bool active = l < g.bvol;
-  const SX* xr = x + (long long)blockIdx.y * xs;
-  SY* yr = y + (long long)blockIdx.y * ys;
+  const SX* xr = x + (long long)rhs * xs;
+  SY* yr = y + (long long)rhs * ys;
   int bc[4], lc[4] = {0, 0, 0, 0};
   decode_block(g, b, bc);
   cplx<T> psi[12], acc[12];
@@ -134,7 +138,7 @@ __global__ void __launch_bounds__(MAXT)
     for (int k = 0; k < 12; ++k) {
       const long long idx = spinor_index(g, b, k, l);
       cplx<T> d = scale * (diag * psi[k] - half * acc[k]);
-      if constexpr (MODE == 1) d = ld<T>(bsrc + (long long)blockIdx.y * ys + idx) - d;
+      if constexpr (MODE == 1) d = ld<T>(bsrc + (long long)rhs * ys + idx) - d;
       st(yr + idx, d);
     }
   }
@@ -150,13 +154,14 @@ size_t blk_lds(const Geom& g) {
 template <typename T, typename SX, typename SG, typename SY, int MODE>
 __global__ void __launch_bounds__(kThreads)
     k_dslash(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
-             const SY* __restrict__ bsrc, long long xs, long long ys) {
+             const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist) {
   const int chunk = xcd_remap(blockIdx.x, (int)((g.V + kThreads - 1) / kThreads));
   if (chunk < 0) return;
   const long long s = (long long)chunk * kThreads + threadIdx.x;
   if (s >= g.V) return;
-  const SX* xr = x + (long long)blockIdx.y * xs;
-  SY* yr = y + (long long)blockIdx.y * ys;
+  const int rhs = rlist ? rlist[blockIdx.y] : blockIdx.y;
+  const SX* xr = x + (long long)rhs * xs;
+  SY* yr = y + (long long)rhs * ys;
   const int b = (int)(s / g.bvol);
   const int l = (int)(s - (long long)b * g.bvol);
   int bc[4], lc[4];
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__(kThreads)
     cplx<T> xo = ld<T>(xr + idx);
     cplx<T> d = scale * (diag * xo - half * acc[c]);
     if constexpr (MODE == 1) {
-      const SY* br = bsrc + (long long)blockIdx.y * ys;
+      const SY* br = bsrc + (long long)rhs * ys;
       d = ld<T>(br + idx) - d;
     }
     st(yr + idx, d);
@@ -181,7 +186,7 @@ __global__ void __launch_bounds__(kThreads)
 
 template <typename T, typename SX, typename SG, typename SY, int MODE>
 dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                     long long ys, int nrhs, hipStream_t s);
+                     long long ys, int nrhs, const int* rlist, hipStream_t s);
 
 dim3 grid_for(const Geom& g, int nrhs) {
   return dim3((unsigned)xcd_grid((int)((g.V + kThreads - 1) / kThreads)), (unsigned)nrhs);
@@ -189,7 +194,7 @@ dim3 grid_for(const Geom& g, int nrhs) {
 
 template <typename T, typename SX, typename SG, typename SY, int MODE>
 dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                     long long ys, int nrhs, hipStream_t s) {
+                     long long ys, int nrhs, const int* rlist, hipStream_t s) {
   const size_t lds = blk_lds<T, SX>(g);
   const int threads = ((g.bvol + 63) / 64) * 64;
   if (lds <= 160 * 1024) {
@@ -201,8 +206,8 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
           return DW_EHIP;
         }
       }
-      dim3 grid((unsigned)xcd_grid(g.nblk), (unsigned)nrhs);
-      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys);
+      dim3 grid((unsigned)xcd_grid(g.nblk * nrhs), 1);
+      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist);
       DW_CHECK_LAUNCH();
       return DW_OK;
     };
@@ -211,7 +216,7 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
     return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 1024>);
   }
   hipLaunchKernelGGL((k_dslash<T, SX, SG, SY, MODE>), grid_for(g, nrhs), kThreads, 0, s, g, diag, x, scale, U, y, b,
-                     xs, ys);
+                     xs, ys, nrhs, rlist);
   DW_CHECK_LAUNCH();
   return DW_OK;
 }
@@ -220,7 +225,8 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
 
 dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
                               double* y, const double* b, int mode, int nrhs, long long xs, long long ys,
-                              hipStream_t s) {
+                              hipStream_t s, const int* rlist) {
+  if (nrhs < 1) return DW_OK;
   const double diag = 4.0 + m0;
   const s64* Ug = (const s64*)U64;
   s64* yo = (s64*)y;
@@ -229,12 +235,12 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
   dw_status st;
   if (prec_x == DW_PREC_F64) {
     const s64* xi = (const s64*)x;
-    st = mode == 0 ? launch_any<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s)
-                   : launch_any<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s);
+    st = mode == 0 ? launch_any<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s)
+                   : launch_any<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s);
   } else if (prec_x == DW_PREC_F32) {
     const s32* xi = (const s32*)x;
-    st = mode == 0 ? launch_any<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s)
-                   : launch_any<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, s);
+    st = mode == 0 ? launch_any<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s)
+                   : launch_any<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s);
   } else {
     set_error("outer dslash input precision must be F64 or F32");
     return DW_EINVAL;
@@ -254,19 +260,19 @@ dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, 
   switch (prec) {
     case DW_PREC_F64:
       st = launch_any<double, s64, s64, s64, 0>(g, 4.0 + m0, (const s64*)x, 1.0, (const s64*)U, (s64*)y, nullptr, sd,
-                                                sd, nrhs, s);
+                                                sd, nrhs, nullptr, s);
       break;
     case DW_PREC_F32:
       st = launch_any<float, s32, s32, s32, 0>(g, df, (const s32*)x, 1.0f, (const s32*)U, (s32*)y, nullptr, sd, sd,
-                                               nrhs, s);
+                                               nrhs, nullptr, s);
       break;
     case DW_PREC_F16:
       st = launch_any<float, s16, s16, s16, 0>(g, df, (const s16*)x, 1.0f, (const s16*)U, (s16*)y, nullptr, sd, sd,
-                                               nrhs, s);
+                                               nrhs, nullptr, s);
       break;
     case DW_PREC_BF16:
       st = launch_any<float, sbf, sbf, sbf, 0>(g, df, (const sbf*)x, 1.0f, (const sbf*)U, (sbf*)y, nullptr, sd, sd,
-                                               nrhs, s);
+                                               nrhs, nullptr, s);
       break;
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }

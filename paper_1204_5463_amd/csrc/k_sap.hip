@@ -36,7 +36,7 @@ __device__ __forceinline__ T wave_sum(T a) {
 template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL>
 __global__ void __launch_bounds__(MAXT)
     k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
-                 int nmr, int z_zero, long long vs, long long zs) {
+                 int nmr, int z_zero, long long vs, long long zs, int nr, const int* __restrict__ rlist) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // LDS: [links 36 x bvol (LDSL)] [rho 12 x bvol] [reduction 2 x nw x 3]
   SG* lks = reinterpret_cast<SG*>(smem);
@@ -44,15 +44,19 @@ __global__ void __launch_bounds__(MAXT)
   cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem + lbytes);
   const int nw = blockDim.x / kWave;
   T* red = reinterpret_cast<T*>(rho_s + 12 * g.bvol);
-  const int jb = xcd_remap(blockIdx.x, g.nbc);
-  if (jb < 0) return;  // whole workgroup: uniform exit before any barrier
+  // work item -> (block, right-hand side) with the RHS index fastest, so that
+  // workgroups sharing a block's links run together on one XCD
+  const int wi = xcd_remap(blockIdx.x, g.nbc * nr);
+  if (wi < 0) return;  // whole workgroup: uniform exit before any barrier
+  const int jb = wi / nr;
+  const int rhs = rlist ? rlist[wi - jb * nr] : wi - jb * nr;
   const int b = colour_block(g, colour, jb);
   const int l = threadIdx.x;
   const bool active = l < g.bvol;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const SV* vr = v + (long long)blockIdx.y * vs;
-  SZ* zr = z + (long long)blockIdx.y * zs;
+  const SV* vr = v + (long long)rhs * vs;
+  SZ* zr = z + (long long)rhs * zs;
   const T half = (T)0.5;
 
   int bc[4], lc[4] = {0, 0, 0, 0};
@@ -169,7 +173,7 @@ __global__ void __launch_bounds__(MAXT)
 
 template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL>
 dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, hipStream_t s) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
   const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
   const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
   const size_t shmem =
@@ -186,10 +190,10 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
       return DW_EHIP;
     }
   }
-  dim3 grid((unsigned)xcd_grid(g.nbc), (unsigned)nrhs);
+  dim3 grid((unsigned)xcd_grid(g.nbc * nrhs), 1);
   KTimer kt(DW_K_SAP, s);
   hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
-                     (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs);
+                     (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs, nrhs, rlist);
   DW_CHECK_LAUNCH();
   // algorithmic traffic per site of this colour: v, 4 links, z read (or the
   // other colour's z cleared) and z written; flops: block residual stencil
@@ -205,34 +209,36 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
 
 template <typename T, typename SV, typename SZ, typename SG, int MAXT>
 dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, hipStream_t s) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
   // Stage the block's links in LDS only when that keeps several workgroups
   // per CU: the MR steps are VALU bound and lose more to lower occupancy
   // than they gain from fewer cached link reads (measured on 4^4 blocks
   // with FP16 links: 380 us with links from L1/L2, 517 us staged).
   const size_t need = (size_t)36 * g.bvol * sizeof(SG) + (size_t)12 * g.bvol * sizeof(cplx<T>) + 512;
   if (need <= 40 * 1024)
-    return launch_t<T, SV, SZ, SG, MAXT, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-  return launch_t<T, SV, SZ, SG, MAXT, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+    return launch_t<T, SV, SZ, SG, MAXT, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+  return launch_t<T, SV, SZ, SG, MAXT, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
 }
 
 template <typename T, typename SV, typename SZ, typename SG>
 dw_status launch(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                 int nrhs, long long vs, long long zs, hipStream_t s) {
-  if (g.bvol <= 256) return launch_m<T, SV, SZ, SG, 256>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-  if (g.bvol <= 512) return launch_m<T, SV, SZ, SG, 512>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-  return launch_m<T, SV, SZ, SG, 1024>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+                 int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
+  if (g.bvol <= 256) return launch_m<T, SV, SZ, SG, 256>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+  if (g.bvol <= 512) return launch_m<T, SV, SZ, SG, 512>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+  return launch_m<T, SV, SZ, SG, 1024>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
 }
 
 }  // namespace
 
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
-                            int nmr, int z_zero, int nrhs, long long vs, long long zs, hipStream_t s) {
+                            int nmr, int z_zero, int nrhs, long long vs, long long zs, hipStream_t s,
+                            const int* rlist) {
+  if (nrhs < 1) return DW_OK;
   switch (prec) {
-    case DW_PREC_F64: return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-    case DW_PREC_F32: return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-    case DW_PREC_F16: return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
-    case DW_PREC_BF16: return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, s);
+    case DW_PREC_F64: return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+    case DW_PREC_F32: return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+    case DW_PREC_F16: return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+    case DW_PREC_BF16: return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
 }

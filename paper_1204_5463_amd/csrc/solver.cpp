@@ -33,6 +33,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -47,186 +48,277 @@ using namespace dw;
 
 namespace {
 
+// Device and host state of a batch of right-hand sides solved in lock-step.
 struct Work {
-  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal;
-  double* scal_h = nullptr;
+  int nr = 0, m = 0;
+  long long n = 0;
+  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal, rlist;
+  double* scal_h = nullptr;  // nr x (kSclCount + 2): scalars and the pair nrm
+  int* rlist_h = nullptr;
   ~Work() {
     if (scal_h) (void)hipHostFree(scal_h);
+    if (rlist_h) (void)hipHostFree(rlist_h);
   }
+  double* Vr(int r) const { return V.as<double>() + 2 * (long long)r * (m + 1) * n; }
+  double* Zr(int r) const { return Z.as<double>() + 2 * (long long)r * m * n; }
+  double* vec(const DevBuf& d, int r) const { return d.as<double>() + 2 * (long long)r * n; }
+  double* Hr(int r) const { return H.as<double>() + 2 * (long long)r * kLd * kMaxM; }
+  double* cr(int r) const { return c.as<double>() + 2 * (long long)r * kLd; }
+  double* etar(int r) const { return eta.as<double>() + 2 * (long long)r * kMaxM; }
+  double* redr(int r) const { return red.as<double>() + 2 * (long long)r * (2 * kLd + 6); }
+  double* coefr(int r) const { return coef.as<double>() + 2 * (long long)r * (2 * kLd + 4); }
+  double* nrmr(int r) const { return nrm.as<double>() + 2 * (long long)r; }
+  double* Qr(int r) const { return Q.as<double>() + 2 * (long long)r * kLd * 25; }
+  double* ritzr(int r) const { return ritz.as<double>() + 2 * (long long)r * kMaxM; }
+  double* scalr(int r) const { return scal.as<double>() + (long long)r * kSclCount; }
+  double* partr(int r) const { return partials.as<double>() + 2 * (long long)r * (2 * kLd + 6) * kBlasGrid; }
+  const double* sh(int r) const { return scal_h + (long long)r * (kSclCount + 2); }
 };
 
-dw_status alloc_work(dw_field f, const fgmresdr_params* P, Work& W, hipStream_t s) {
+size_t bytes_per_rhs(long long n, int m, int prec) {
+  const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
+  return (size_t)n * 16 * ((m + 1) + m + 4) + (size_t)n * pair_bytes(prec) +
+         (zprec != DW_PREC_F64 ? (size_t)n * pair_bytes(zprec) : 0) + (size_t)(2 * kLd + 6) * kBlasGrid * 16;
+}
+
+dw_status alloc_work(dw_field f, const fgmresdr_params* P, int nr, Work& W, hipStream_t s) {
   const long long n = f->g.V * 12;
   const int prec = P->sap.storage;
   const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
   dw_ctx ctx = f->ctx;
-  DW_TRY(W.V.alloc(ctx, (size_t)(P->m + 1) * n * 16, s));
-  DW_TRY(W.Z.alloc(ctx, (size_t)P->m * n * 16, s));
-  if (zprec != DW_PREC_F64) DW_TRY(W.zs.alloc(ctx, (size_t)n * pair_bytes(zprec), s));
-  DW_TRY(W.w.alloc(ctx, (size_t)n * 16, s));
-  DW_TRY(W.r.alloc(ctx, (size_t)n * 16, s));
-  DW_TRY(W.x.alloc(ctx, (size_t)n * 16, s));
-  DW_TRY(W.b.alloc(ctx, (size_t)n * 16, s));
-  DW_TRY(W.vs.alloc(ctx, (size_t)n * pair_bytes(prec), s));
-  DW_TRY(W.partials.alloc(ctx, (size_t)(2 * kLd + 6) * kBlasGrid * 16, s));
-  DW_TRY(W.H.alloc(ctx, (size_t)kLd * kMaxM * 16, s));
-  DW_TRY(W.c.alloc(ctx, (size_t)kLd * 16, s));
-  DW_TRY(W.eta.alloc(ctx, (size_t)kMaxM * 16, s));
-  DW_TRY(W.red.alloc(ctx, (size_t)(2 * kLd + 6) * 16, s));
-  DW_TRY(W.coef.alloc(ctx, (size_t)(2 * kLd + 4) * 16, s));
-  DW_TRY(W.nrm.alloc(ctx, 16, s));
-  DW_TRY(W.Q.alloc(ctx, (size_t)kLd * 25 * 16, s));
-  DW_TRY(W.ritz.alloc(ctx, (size_t)kMaxM * 16, s));
-  DW_TRY(W.scal.alloc(ctx, (size_t)kSclCount * 8, s));
-  DW_CHECK_HIP(hipHostMalloc((void**)&W.scal_h, 16 * sizeof(double), hipHostMallocDefault));
+  W.nr = nr;
+  W.m = P->m;
+  W.n = n;
+  DW_TRY(W.V.alloc(ctx, (size_t)nr * (P->m + 1) * n * 16, s));
+  DW_TRY(W.Z.alloc(ctx, (size_t)nr * P->m * n * 16, s));
+  if (zprec != DW_PREC_F64) DW_TRY(W.zs.alloc(ctx, (size_t)nr * n * pair_bytes(zprec), s));
+  DW_TRY(W.w.alloc(ctx, (size_t)nr * n * 16, s));
+  DW_TRY(W.r.alloc(ctx, (size_t)nr * n * 16, s));
+  DW_TRY(W.x.alloc(ctx, (size_t)nr * n * 16, s));
+  DW_TRY(W.b.alloc(ctx, (size_t)nr * n * 16, s));
+  DW_TRY(W.vs.alloc(ctx, (size_t)nr * n * pair_bytes(prec), s));
+  DW_TRY(W.partials.alloc(ctx, (size_t)nr * (2 * kLd + 6) * kBlasGrid * 16, s));
+  DW_TRY(W.H.alloc(ctx, (size_t)nr * kLd * kMaxM * 16, s));
+  DW_TRY(W.c.alloc(ctx, (size_t)nr * kLd * 16, s));
+  DW_TRY(W.eta.alloc(ctx, (size_t)nr * kMaxM * 16, s));
+  DW_TRY(W.red.alloc(ctx, (size_t)nr * (2 * kLd + 6) * 16, s));
+  DW_TRY(W.coef.alloc(ctx, (size_t)nr * (2 * kLd + 4) * 16, s));
+  DW_TRY(W.nrm.alloc(ctx, (size_t)nr * 16, s));
+  DW_TRY(W.Q.alloc(ctx, (size_t)nr * kLd * 25 * 16, s));
+  DW_TRY(W.ritz.alloc(ctx, (size_t)nr * kMaxM * 16, s));
+  DW_TRY(W.scal.alloc(ctx, (size_t)nr * kSclCount * 8, s));
+  DW_TRY(W.rlist.alloc(ctx, (size_t)nr * sizeof(int), s));
+  DW_CHECK_HIP(hipHostMalloc((void**)&W.scal_h, (size_t)nr * (kSclCount + 2) * sizeof(double), hipHostMallocDefault));
+  DW_CHECK_HIP(hipHostMalloc((void**)&W.rlist_h, (size_t)nr * sizeof(int), hipHostMallocDefault));
   return DW_OK;
 }
 
-// reads scal (kSclCount doubles) and nrm (one pair) to the host
+// reads every RHS's scalars and squared norm to the host (one sync)
 dw_status readback(Work& W, hipStream_t s) {
-  DW_CHECK_HIP(hipMemcpyAsync(W.scal_h, W.scal.p, kSclCount * sizeof(double), hipMemcpyDeviceToHost, s));
-  DW_CHECK_HIP(hipMemcpyAsync(W.scal_h + kSclCount, W.nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  for (int r = 0; r < W.nr; ++r) {
+    DW_CHECK_HIP(hipMemcpyAsync(W.scal_h + (long long)r * (kSclCount + 2), W.scalr(r), kSclCount * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    DW_CHECK_HIP(hipMemcpyAsync(W.scal_h + (long long)r * (kSclCount + 2) + kSclCount, W.nrmr(r), 2 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+  }
   DW_CHECK_HIP(hipStreamSynchronize(s));
   prof_flush();
   return DW_OK;
 }
 
-dw_status solve_one(dw_field f, double m0, const fgmresdr_params* P, const double* b_can, double* x_can, Work& W,
-                    dw_solve_stats* st, hipStream_t s) {
+// uploads the list of participating RHS; the pinned host copy is reused only
+// after the next synchronisation, which every step performs
+dw_status set_rlist(Work& W, const std::vector<int>& list, hipStream_t s) {
+  for (size_t i = 0; i < list.size(); ++i) W.rlist_h[i] = list[i];
+  DW_CHECK_HIP(hipMemcpyAsync(W.rlist.p, W.rlist_h, list.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  return DW_OK;
+}
+
+struct Rhs {
+  int j0 = 0, jend = 0, iters = 0, cycles = 0, clean = 0;
+  bool lagged = false, broke = false, frozen = false, done = false, converged = false, fresh = true;
+  double bnorm = 0, res_e = 0, res_i = 0;
+};
+
+// Solves nr right-hand sides in lock-step: at Arnoldi step j every RHS whose
+// current cycle covers j takes part; the SAP sweeps and the FP64 operator
+// cover all of them in one launch (each link read serves every RHS through
+// L2), the Gram-Schmidt and small dense kernels run per RHS, and one host
+// synchronisation per step serves the whole batch.
+dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const double* b_can, double* x_can, int nr,
+                      Work& W, dw_solve_stats* st, hipStream_t s) {
   const Geom& g = f->g;
   const long long n = g.V * 12;
   const int m = P->m, k = P->k;
   const int prec = P->sap.storage;
   const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;  // SAP accumulator
-  const size_t zb = 16;                                                  // Z is FP64
   const double sigma = prec == DW_PREC_F64 ? 1.0 : sqrt((double)n);
   const double bd_tol = 1e-14;
-  double* V = W.V.as<double>();
-  char* Z = W.Z.as<char>();
-  double* partials = W.partials.as<double>();
-  double* scal = W.scal.as<double>();
   auto t0 = std::chrono::steady_clock::now();
+  std::vector<Rhs> R(nr);
 
-  DW_TRY(launch_pack_spinor(g, DW_PREC_F64, b_can, W.b.p, 1.0, 1, s));
-  DW_CHECK_HIP(hipMemsetAsync(W.x.p, 0, (size_t)n * 16, s));
-  DW_TRY(blas_dots(DW_PREC_F64, W.b.p, n, 1, W.b.as<double>(), n, partials, W.nrm.as<double>(), 1, 0, s));
+  DW_TRY(launch_pack_spinor(g, DW_PREC_F64, b_can, W.b.p, 1.0, nr, s));
+  DW_CHECK_HIP(hipMemsetAsync(W.x.p, 0, (size_t)nr * n * 16, s));
+  for (int r = 0; r < nr; ++r)
+    DW_TRY(blas_dots(DW_PREC_F64, W.vec(W.b, r), n, 1, W.vec(W.b, r), n, W.partr(r), W.nrmr(r), 1, 0, s));
+  DW_CHECK_HIP(hipMemcpyAsync(W.r.p, W.b.p, (size_t)nr * n * 16, hipMemcpyDeviceToDevice, s));
   DW_TRY(readback(W, s));
-  const double bnorm = sqrt(W.scal_h[kSclCount]);
-  memset(st, 0, sizeof *st);
-  if (bnorm == 0.0) {
-    DW_CHECK_HIP(hipMemsetAsync(x_can, 0, (size_t)n * 16, s));
-    DW_CHECK_HIP(hipStreamSynchronize(s));
-    st->converged = 1;
-    return DW_OK;
-  }
-  DW_CHECK_HIP(hipMemcpyAsync(W.r.p, W.b.p, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
-
-  int iters = 0, cycles = 0, clean = 0;
-  double res_e = bnorm, res_i = bnorm;
-  bool fresh = true, converged = false;
-  while (true) {
-    int j0;
-    if (fresh) {
-      // nrm holds ||r||^2 of the current explicit residual
-      DW_TRY(dense_fresh(W.H.as<double>(), W.c.as<double>(), W.nrm.as<double>(), scal, s));
-      DW_TRY(blas_scale(W.r.as<double>(), V, scal + kSclBetaInv, n, s));
-      j0 = 0;
-    } else {
-      j0 = k;
+  for (int r = 0; r < nr; ++r) {
+    R[r].bnorm = sqrt(W.sh(r)[kSclCount]);
+    R[r].res_e = R[r].res_i = R[r].bnorm;
+    if (R[r].bnorm == 0.0) {
+      R[r].done = R[r].converged = true;
     }
-    int jend = j0;
-    bool broke = false;
-    bool lagged = false;  // V_j holds a once-orthogonalised, unnormalised vector
-    double* red = W.red.as<double>();
-    double* coef = W.coef.as<double>();
-    for (int j = j0; j < m; ++j) {
-      double* vj = V + 2 * (long long)j * n;
-      double* vnext = V + 2 * (long long)(j + 1) * n;
-      double* zj = (double*)(Z + (size_t)j * n * zb);
-      void* zacc = zprec == DW_PREC_F64 ? (void*)zj : W.zs.p;
-      // z_j = M_j applied to sigma * v_j (the lagged vector scaled by its
+  }
+
+  std::vector<int> part;
+  while (true) {
+    // ---- cycle start
+    std::vector<int> cyc;
+    for (int r = 0; r < nr; ++r) {
+      Rhs& q = R[r];
+      if (q.done) continue;
+      cyc.push_back(r);
+      if (q.fresh) {
+        // W.nrm(r) holds ||r||^2 of the current explicit residual
+        DW_TRY(dense_fresh(W.Hr(r), W.cr(r), W.nrmr(r), W.scalr(r), s));
+        DW_TRY(blas_scale(W.vec(W.r, r), W.Vr(r), W.scalr(r) + kSclBetaInv, n, s));
+        q.j0 = 0;
+      } else {
+        q.j0 = k;
+      }
+      q.jend = q.j0;
+      q.lagged = q.broke = q.frozen = false;
+    }
+    if (cyc.empty()) break;
+    int jmin = m;
+    for (int r : cyc) jmin = std::min(jmin, R[r].j0);
+
+    // ---- lock-step Arnoldi steps
+    for (int j = jmin; j < m; ++j) {
+      part.clear();
+      for (int r : cyc)
+        if (!R[r].frozen && R[r].j0 <= j) part.push_back(r);
+      if (part.empty()) break;
+      DW_TRY(set_rlist(W, part, s));
+      const int np = (int)part.size();
+      // z_j = M_j applied to sigma * v_j (lagged vectors scaled by their
       // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
-      DW_TRY(launch_convert(DW_PREC_F64, vj, prec, W.vs.p, sigma, n, s, lagged ? scal + kSclHinv : nullptr));
-      for (int cyc = 0; cyc < P->sap.ncycles; ++cyc)
+      for (int r : part)
+        DW_TRY(launch_convert(DW_PREC_F64, W.Vr(r) + 2 * (long long)j * n, prec,
+                              (char*)W.vs.p + (size_t)r * n * pair_bytes(prec), sigma, n, s,
+                              R[r].lagged ? W.scalr(r) + kSclHinv : nullptr));
+      void* zacc = zprec == DW_PREC_F64 ? (void*)(W.Z.as<double>() + 2 * (long long)j * n) : W.zs.p;
+      const long long zstride = zprec == DW_PREC_F64 ? (long long)m * n : n;
+      for (int cy = 0; cy < P->sap.ncycles; ++cy)
         for (int colour = 0; colour < 2; ++colour)
           DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
-                                   cyc == 0 && colour == 0 ? 1 : 0, 1, n, n, s));
-      if (zprec != DW_PREC_F64) DW_TRY(launch_convert(zprec, zacc, DW_PREC_F64, zj, 1.0 / sigma, n, s));
-      // w = D z_j in FP64 on the stored z_j
-      DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, zj, 1.0, f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, 1, n,
-                                 n, s));
-      // Gram-Schmidt with delayed reorthogonalisation: one sweep of dot
-      // products finalises v_j (second pass) and projects w (first pass),
-      // one update sweep writes v_j and the next lagged vector w'.
-      const int nv = lagged ? j : j + 1;
-      DW_TRY(gs_reduce(V, n, nv, lagged ? vj : nullptr, W.w.as<double>(), n, partials, red, s));
-      DW_TRY(dense_gs_coef(W.H.as<double>(), nv, lagged ? j : -1, j, lagged ? 1 : 0, 1, red, coef, scal, bd_tol, s));
-      DW_TRY(gs_update(V, n, nv, lagged ? j : -1, W.w.as<double>(), vnext, coef, n, partials, W.nrm.as<double>(), s));
-      DW_TRY(dense_step2(W.H.as<double>(), j, W.nrm.as<double>(), W.c.as<double>(), scal, bd_tol, s));
-      lagged = true;
-      ++iters;
-      jend = j + 1;
+                                   cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, W.rlist.as<int>()));
+      if (zprec != DW_PREC_F64)
+        for (int r : part)
+          DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), DW_PREC_F64,
+                                W.Zr(r) + 2 * (long long)j * n, 1.0 / sigma, n, s));
+      // w = D z_j in FP64 on the stored z_j, all participants in one launch
+      DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.Z.as<double>() + 2 * (long long)j * n, 1.0,
+                                 f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, np, (long long)m * n, n, s,
+                                 W.rlist.as<int>()));
+      // Gram-Schmidt with delayed reorthogonalisation, per RHS
+      for (int r : part) {
+        Rhs& q = R[r];
+        double* V = W.Vr(r);
+        const int nv = q.lagged ? j : j + 1;
+        double* vj = V + 2 * (long long)j * n;
+        DW_TRY(gs_reduce(V, n, nv, q.lagged ? vj : nullptr, W.vec(W.w, r), n, W.partr(r), W.redr(r), s));
+        DW_TRY(dense_gs_coef(W.Hr(r), nv, q.lagged ? j : -1, j, q.lagged ? 1 : 0, 1, W.redr(r), W.coefr(r),
+                             W.scalr(r), bd_tol, s));
+        DW_TRY(gs_update(V, n, nv, q.lagged ? j : -1, W.vec(W.w, r), V + 2 * (long long)(j + 1) * n, W.coefr(r), n,
+                         W.partr(r), W.nrmr(r), s));
+        DW_TRY(dense_step2(W.Hr(r), j, W.nrmr(r), W.cr(r), W.scalr(r), bd_tol, s));
+      }
       DW_TRY(readback(W, s));
-      res_i = W.scal_h[kSclResImp];
-      broke = W.scal_h[kSclBreak] != 0.0;
-      if (broke || res_i <= P->tol * bnorm || iters >= P->max_iter) break;
+      for (int r : part) {
+        Rhs& q = R[r];
+        q.lagged = true;
+        ++q.iters;
+        q.jend = j + 1;
+        q.res_i = W.sh(r)[kSclResImp];
+        q.broke = W.sh(r)[kSclBreak] != 0.0;
+        if (q.broke || q.res_i <= P->tol * q.bnorm || q.iters >= P->max_iter) q.frozen = true;
+      }
     }
-    // finalise the last lagged vector (second Gram-Schmidt pass) so that
-    // V_{jend+1} is orthonormal and H^ exact; after a breakdown it is unused
-    if (lagged && !broke) {
-      double* vl = V + 2 * (long long)jend * n;
-      DW_TRY(gs_reduce(V, n, jend, vl, nullptr, n, partials, red, s));
-      DW_TRY(dense_gs_coef(W.H.as<double>(), jend, jend, -1, 1, 0, red, coef, scal, bd_tol, s));
-      DW_TRY(gs_update(V, n, jend, jend, nullptr, nullptr, coef, n, partials, nullptr, s));
-    }
+
+    // ---- cycle end: finalise the last lagged vector (second GS pass), then
     // iterate and explicit FP64 residual
-    DW_TRY(dense_lsq(W.H.as<double>(), jend, W.c.as<double>(), W.eta.as<double>(), scal, s));
-    DW_TRY(blas_combine(DW_PREC_F64, Z, n, jend, W.eta.as<double>(), 1.0, W.x.as<double>(), n, s));
-    DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.x.p, 1.0, f->U[DW_PREC_F64], W.r.as<double>(),
-                               W.b.as<double>(), 1, 1, n, n, s));
-    DW_TRY(blas_dots(DW_PREC_F64, W.r.p, n, 1, W.r.as<double>(), n, partials, W.nrm.as<double>(), 1, 0, s));
+    for (int r : cyc) {
+      Rhs& q = R[r];
+      double* V = W.Vr(r);
+      if (q.lagged && !q.broke) {
+        double* vl = V + 2 * (long long)q.jend * n;
+        DW_TRY(gs_reduce(V, n, q.jend, vl, nullptr, n, W.partr(r), W.redr(r), s));
+        DW_TRY(dense_gs_coef(W.Hr(r), q.jend, q.jend, -1, 1, 0, W.redr(r), W.coefr(r), W.scalr(r), bd_tol, s));
+        DW_TRY(gs_update(V, n, q.jend, q.jend, nullptr, nullptr, W.coefr(r), n, W.partr(r), nullptr, s));
+      }
+      DW_TRY(dense_lsq(W.Hr(r), q.jend, W.cr(r), W.etar(r), W.scalr(r), s));
+      DW_TRY(blas_combine(DW_PREC_F64, W.Zr(r), n, q.jend, W.etar(r), 1.0, W.vec(W.x, r), n, s));
+    }
+    DW_TRY(set_rlist(W, cyc, s));
+    DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.x.p, 1.0, f->U[DW_PREC_F64], W.r.as<double>(), W.b.as<double>(),
+                               1, (int)cyc.size(), n, n, s, W.rlist.as<int>()));
+    for (int r : cyc)
+      DW_TRY(blas_dots(DW_PREC_F64, W.vec(W.r, r), n, 1, W.vec(W.r, r), n, W.partr(r), W.nrmr(r), 1, 0, s));
     DW_TRY(readback(W, s));
-    res_i = W.scal_h[kSclResImp];
-    res_e = sqrt(W.scal_h[kSclCount]);
-    ++cycles;
-    if (res_e <= P->tol * bnorm) {
-      converged = true;
-      break;
+    std::vector<int> defl;
+    for (int r : cyc) {
+      Rhs& q = R[r];
+      q.res_i = W.sh(r)[kSclResImp];
+      q.res_e = sqrt(W.sh(r)[kSclCount]);
+      ++q.cycles;
+      q.fresh = true;
+      if (q.res_e <= P->tol * q.bnorm) {
+        q.done = q.converged = true;
+      } else if (q.iters >= P->max_iter) {
+        q.done = true;
+      } else if (k == 0) {
+        // plain restarted FGMRES(m)
+      } else if (q.broke || q.jend <= k || q.res_e > P->restart_t * fmax(q.res_i, 1e-300)) {
+        ++q.clean;  // clean restart (Section 4.7)
+      } else {
+        defl.push_back(r);
+      }
     }
-    if (iters >= P->max_iter) break;
-    if (k == 0) {
-      fresh = true;
-      continue;
+    if (!defl.empty()) {
+      for (int r : defl)
+        DW_TRY(dense_deflate(W.Hr(r), R[r].jend, k, W.cr(r), W.etar(r), W.Qr(r), W.ritzr(r), W.scalr(r), s));
+      DW_TRY(readback(W, s));
+      for (int r : defl) {
+        Rhs& q = R[r];
+        if (W.sh(r)[kSclStatus] != 0.0) {
+          ++q.clean;
+          continue;
+        }
+        DW_TRY(blas_rotate(DW_PREC_F64, W.Vr(r), n, q.jend + 1, W.Qr(r), kLd, k + 1, n, s));
+        DW_TRY(blas_rotate(DW_PREC_F64, W.Zr(r), n, q.jend, W.Qr(r), kLd, k, n, s));
+        DW_CHECK_HIP(hipMemsetAsync(W.cr(r), 0, (size_t)kLd * 16, s));
+        DW_TRY(blas_dots(DW_PREC_F64, W.Vr(r), n, k + 1, W.vec(W.r, r), n, W.partr(r), W.cr(r), 1, 0, s));
+        q.fresh = false;
+      }
     }
-    if (broke || jend <= k || res_e > P->restart_t * fmax(res_i, 1e-300)) {
-      ++clean;
-      fresh = true;
-      continue;
-    }
-    DW_TRY(dense_deflate(W.H.as<double>(), jend, k, W.c.as<double>(), W.eta.as<double>(), W.Q.as<double>(),
-                         W.ritz.as<double>(), scal, s));
-    DW_TRY(readback(W, s));
-    if (W.scal_h[kSclStatus] != 0.0) {
-      ++clean;
-      fresh = true;
-      continue;
-    }
-    DW_TRY(blas_rotate(DW_PREC_F64, V, n, jend + 1, W.Q.as<double>(), kLd, k + 1, n, s));
-    DW_TRY(blas_rotate(DW_PREC_F64, Z, n, jend, W.Q.as<double>(), kLd, k, n, s));
-    DW_CHECK_HIP(hipMemsetAsync(W.c.p, 0, (size_t)kLd * 16, s));
-    DW_TRY(blas_dots(DW_PREC_F64, V, n, k + 1, W.r.as<double>(), n, partials, W.c.as<double>(), 1, 0, s));
-    fresh = false;
   }
-  DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, W.x.p, x_can, 1.0, 1, s));
+  DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, W.x.p, x_can, 1.0, nr, s));
   DW_CHECK_HIP(hipStreamSynchronize(s));
-  auto t1 = std::chrono::steady_clock::now();
-  st->converged = converged ? 1 : 0;
-  st->iterations = iters;
-  st->cycles = cycles;
-  st->clean_restarts = clean;
-  st->true_relres = res_e / bnorm;
-  st->implicit_relres = res_i / bnorm;
-  st->seconds = std::chrono::duration<double>(t1 - t0).count();
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int r = 0; r < nr; ++r) {
+    const Rhs& q = R[r];
+    dw_solve_stats& o = st[r];
+    memset(&o, 0, sizeof o);
+    o.converged = q.converged ? 1 : 0;
+    o.iterations = q.iters;
+    o.cycles = q.cycles;
+    o.clean_restarts = q.clean;
+    o.true_relres = q.bnorm > 0 ? q.res_e / q.bnorm : 0.0;
+    o.implicit_relres = q.bnorm > 0 ? q.res_i / q.bnorm : 0.0;
+    o.seconds = secs;
+  }
   return DW_OK;
 }
 
@@ -256,15 +348,24 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
   DW_CHECK_HIP(hipGetDevice(&cur));
   if (cur != f->ctx->device) DW_CHECK_HIP(hipSetDevice(f->ctx->device));
   ProfScope ps(f->ctx);
-  Work W;
-  DW_TRY(alloc_work(f, P, W, stream));
   const long long n = f->g.V * 12;
+  // RHS per batch: as many as fit in free device memory (at least one)
+  size_t free_b = 0, total_b = 0;
+  DW_CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t per = bytes_per_rhs(n, P->m, P->sap.storage);
+  int nb = (int)std::max<size_t>(1, (size_t)(0.9 * (double)free_b) / per);
+  nb = std::min(nb, (int)nrhs);
   bool all_conv = true;
+  std::vector<dw_solve_stats> st(nrhs);
+  for (int r0 = 0; r0 < nrhs; r0 += nb) {
+    const int nr = std::min(nb, nrhs - r0);
+    Work W;
+    DW_TRY(alloc_work(f, P, nr, W, stream));
+    DW_TRY(solve_batch(f, m0, P, b + 2 * (long long)r0 * n, x + 2 * (long long)r0 * n, nr, W, st.data() + r0, stream));
+  }
   for (int r = 0; r < nrhs; ++r) {
-    dw_solve_stats st;
-    DW_TRY(solve_one(f, m0, P, b + 2 * (long long)r * n, x + 2 * (long long)r * n, W, &st, stream));
-    if (stats) stats[r] = st;
-    all_conv = all_conv && st.converged;
+    if (stats) stats[r] = st[r];
+    all_conv = all_conv && st[r].converged;
   }
   if (!all_conv) {
     set_error("fgmresdr_solve: max_iter reached before the tolerance");

@@ -114,3 +114,23 @@ def test_multi_rhs_matches_single(c1):
         assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(bb[r])
     x1, _ = f.solve(M01, _params(P.DW_PREC_F32), P.to_device(bb[1]))
     assert np.linalg.norm(x1.cpu().numpy() - x[1]) <= 1e-9 * np.linalg.norm(x[1])
+
+
+@pytest.mark.parametrize("prec", [P.DW_PREC_F64, P.DW_PREC_F16])
+def test_lockstep_batch_equals_single_solves(c1, prec):
+    """RHS solved in lock-step share launches but not arithmetic: each must
+    equal its own single-RHS solve bit for bit (a zero RHS, an easy and a
+    harder one, so that RHS leave the batch at different times)."""
+    U, b, f, xo, info = c1
+    b2 = synth.point_source_noise(L1, 5, seed=77)
+    bb = np.stack([b, np.zeros_like(b), b2, 3.0 * synth.gaussian_spinor(L1, 1009)])
+    prm = _params(prec, m=12, k=4)
+    x, st = f.solve(M01, prm, P.to_device(bb))
+    x = x.cpu().numpy()
+    assert st[1].converged and st[1].iterations == 0 and np.count_nonzero(x[1]) == 0
+    for r in (0, 2, 3):
+        x1, s1 = f.solve(M01, prm, P.to_device(bb[r]))
+        assert st[r].converged and st[r].iterations == s1[0].iterations
+        assert np.array_equal(x1.cpu().numpy(), x[r])
+        res = bb[r] - W.apply_D(U, M01, x[r])
+        assert np.linalg.norm(res) <= 1.01e-10 * np.linalg.norm(bb[r])
