@@ -178,6 +178,63 @@ dw_status sap_precondition(dw_field field, double m0, const sap_params* sap, con
 dw_status fgmresdr_solve(dw_field field, double m0, const fgmresdr_params* params, const double* b, double* x,
                          int32_t nrhs, dw_solve_stats* stats, hipStream_t stream);
 
+/* ---- serving loop ----------------------------------------------------------
+ * A server solves requests of different lattices, masses and RHS counts
+ * with continuous batching: requests are queued in arrival order and
+ * admitted when a slot is free and their device-memory footprint fits the
+ * budget beside the requests already running; each slot runs its request
+ * on its own HIP stream, so admitted requests overlap on the device, and
+ * keeps the request's gauge copies and Krylov / deflation state on the
+ * device until the request completes. Server memory is stream-ordered
+ * (hipMallocAsync), independent of the context's allocator. */
+typedef struct dw_server_params {
+  int32_t slots;           /* requests solved concurrently (>= 1) */
+  int32_t queue_capacity;  /* queued, not yet admitted requests; solve_submit returns DW_EBUSY beyond */
+  double budget_bytes;     /* admission budget; 0 = 80% of the device memory free at creation */
+} dw_server_params;
+
+/* A solve request. The pointers are device pointers owned by the caller;
+ * they must stay valid and unmodified until solve_poll reports
+ * DW_REQ_DONE or DW_REQ_FAILED (the server reads U and b and writes x). */
+typedef struct dw_request {
+  int32_t L[4];           /* lattice extents */
+  int32_t block[4];       /* SAP block extents (params.sap.block must match) */
+  double m0;              /* mass */
+  const double* U;        /* canonical gauge field, complex128 */
+  int32_t nrhs;           /* right-hand sides (solved in lock-step) */
+  int32_t reserved;
+  const double* b;        /* canonical spinors, nrhs fields */
+  double* x;              /* solutions, nrhs fields */
+  fgmresdr_params params; /* solver parameters */
+} dw_request;
+
+typedef enum { DW_REQ_QUEUED = 0, DW_REQ_RUNNING = 1, DW_REQ_DONE = 2, DW_REQ_FAILED = 3 } dw_req_state;
+
+/* Request timing (seconds on the server's steady clock). */
+typedef struct dw_request_times {
+  double queued;    /* submit -> admission */
+  double running;   /* admission -> completion */
+  double latency;   /* submit -> completion */
+} dw_request_times;
+
+dw_status dw_server_create(dw_ctx ctx, const dw_server_params* params, dw_server* out);
+/* Waits for all admitted and queued requests, then frees the server. */
+dw_status dw_server_destroy(dw_server server);
+/* Device-memory footprint the server charges for a request (bytes): the
+ * field's four link copies, the solver's Krylov bases and work vectors for
+ * nrhs right-hand sides, and small per-RHS buffers. 0 if the request is
+ * invalid. Host-only arithmetic (no GPU work). */
+size_t dw_request_footprint(const dw_request* req);
+/* Queues a request (non-blocking). DW_EINVAL: bad geometry or parameters,
+ * or footprint above the budget; DW_EBUSY: queue full. */
+dw_status solve_submit(dw_server server, const dw_request* req, uint64_t* ticket);
+/* Non-blocking status of a ticket. When DONE, stats (nrhs entries, may be
+ * NULL) and times (may be NULL) are filled and the ticket is released, so
+ * a later poll of it returns DW_ENOTFOUND. A FAILED request's error text is
+ * returned by dw_last_error() of the polling thread. */
+dw_status solve_poll(dw_server server, uint64_t ticket, dw_req_state* state, dw_solve_stats* stats,
+                     dw_request_times* times);
+
 /* ---- per-kernel-class timing ---------------------------------------------
  * When enabled on a context, every kernel launch made for that context is
  * bracketed by HIP events on the launch stream; elapsed times are resolved

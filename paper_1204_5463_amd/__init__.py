@@ -22,7 +22,7 @@ import torch
 
 __all__ = [
     "DW_PREC_F64", "DW_PREC_F32", "DW_PREC_F16", "DW_PREC_BF16", "PREC_NAMES",
-    "DwError", "NotConverged", "Context", "Field", "SapParams", "SolverParams", "SolveStats",
+    "DwError", "NotConverged", "Context", "Field", "SapParams", "SolverParams", "SolveStats", "Server",
     "lib", "load",
 ]
 
@@ -70,6 +70,22 @@ class _Stats(ctypes.Structure):
                 ("clean_restarts", ctypes.c_int32), ("true_relres", ctypes.c_double),
                 ("implicit_relres", ctypes.c_double), ("seconds", ctypes.c_double)]
 
+
+class _ServerParams(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("budget_bytes", ctypes.c_double)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("block", ctypes.c_int32 * 4), ("m0", ctypes.c_double),
+                ("U", ctypes.c_void_p), ("nrhs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("params", _SolverParams)]
+
+
+class _ReqTimes(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_double), ("running", ctypes.c_double), ("latency", ctypes.c_double)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -155,6 +171,12 @@ def load(path: str = LIB_PATH):
         "dw_profile_enable": (st, [vp, i32]),
         "dw_profile_get": (st, [vp, i32, ctypes.POINTER(_KStats)]),
         "dw_profile_reset": (st, [vp]),
+        "dw_server_create": (st, [vp, ctypes.POINTER(_ServerParams), ctypes.POINTER(vp)]),
+        "dw_server_destroy": (st, [vp]),
+        "dw_request_footprint": (ctypes.c_size_t, [ctypes.POINTER(_Request)]),
+        "solve_submit": (st, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "solve_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(_Stats),
+                            ctypes.POINTER(_ReqTimes)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -338,6 +360,93 @@ class Field:
             return x, stats
         _check(status, "fgmresdr_solve")
         return x, stats
+
+
+def _request(L, block, m0, U, b, x, params: SolverParams):
+    Lx, Ly, Lz, Lt = (int(v) for v in L)
+    if tuple(U.shape) != (4, Lt, Lz, Ly, Lx, 3, 3):
+        raise ValueError(f"gauge shape {tuple(U.shape)} does not match L={tuple(L)}")
+    vol12 = Lx * Ly * Lz * Lt * 12
+    nrhs = b.numel() // vol12
+    if nrhs * vol12 != b.numel() or x.numel() != b.numel():
+        raise ValueError("b and x must hold a whole number of spinor fields of the lattice")
+    r = _Request()
+    for i in range(4):
+        r.L[i], r.block[i] = (Lx, Ly, Lz, Lt)[i], int(block[i])
+    r.m0, r.nrhs, r.reserved = float(m0), nrhs, 0
+    r.U, r.b, r.x = _dev_ptr(U), _dev_ptr(b), _dev_ptr(x)
+    r.params = params._c()
+    return r
+
+
+class Server:
+    """Continuous-batching solve server: FIFO queue, footprint admission, slots on their own streams.
+
+    submit() returns a ticket; poll() returns None while the request waits or
+    runs, else (x, [SolveStats], times) and forgets the ticket. The server
+    keeps the request's tensors alive until then. Inputs are read on the
+    server's streams, so submit() first waits for the caller's stream.
+    """
+
+    def __init__(self, ctx: Context, slots: int = 2, queue_capacity: int = 64, budget_bytes: float = 0.0):
+        p = _ServerParams(int(slots), int(queue_capacity), float(budget_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().dw_server_create(ctx.handle, ctypes.byref(p), ctypes.byref(h)), "dw_server_create")
+        self.ctx = ctx
+        self.handle = h
+        self._live = {}
+
+    @staticmethod
+    def footprint(L, block, m0, U, b, params: SolverParams, x=None):
+        r = _request(L, block, m0, U, b, b if x is None else x, params)
+        return int(lib().dw_request_footprint(ctypes.byref(r)))
+
+    def submit(self, L, block, m0: float, U: torch.Tensor, b: torch.Tensor, params: SolverParams,
+               x: torch.Tensor | None = None):
+        if x is None:
+            x = torch.empty_like(b)
+        r = _request(L, block, m0, U, b, x, params)
+        torch.cuda.current_stream().synchronize()
+        t = ctypes.c_uint64()
+        _check(lib().solve_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "solve_submit")
+        self._live[t.value] = (U, b, x, r.nrhs)
+        return t.value
+
+    def poll(self, ticket: int):
+        U, b, x, nrhs = self._live[ticket]
+        state = ctypes.c_int32()
+        st = (_Stats * nrhs)()
+        tm = _ReqTimes()
+        _check(lib().solve_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(state), st, ctypes.byref(tm)),
+               "solve_poll")
+        if state.value in (REQ_QUEUED, REQ_RUNNING):
+            return None
+        del self._live[ticket]
+        if state.value == REQ_FAILED:
+            raise DwError(DW_EHIP, "request failed: " + lib().dw_last_error().decode(errors="replace"))
+        stats = [SolveStats(bool(s.converged), s.iterations, s.cycles, s.clean_restarts, s.true_relres,
+                            s.implicit_relres, s.seconds) for s in st]
+        return x, stats, {"queued": tm.queued, "running": tm.running, "latency": tm.latency}
+
+    def wait(self, ticket: int, poll_s: float = 1e-3):
+        import time
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            time.sleep(poll_s)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dw_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def to_device(a, device="cuda"):

@@ -38,6 +38,7 @@ struct dw_field_s {
   dw_ctx ctx;
   dw::Geom g;
   void* U[4];  // links per dw_prec, internal layout
+  hipStream_t stream;  // stream the field was created on (its memory is freed there)
 };
 
 namespace dw {

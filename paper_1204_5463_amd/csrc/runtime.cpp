@@ -123,6 +123,7 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
   }
   f->ctx = ctx;
   f->g = g;
+  f->stream = stream;
   for (int p = 0; p < 4; ++p) f->U[p] = nullptr;
   for (int p = 0; p < 4; ++p) {
     size_t bytes = (size_t)g.V * 36 * pair_bytes(p);
@@ -147,7 +148,7 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
 dw_status dw_field_destroy(dw_field f) {
   clear_error();
   if (!f) return DW_OK;
-  for (int p = 0; p < 4; ++p) dev_free(f->ctx, f->U[p], nullptr);
+  for (int p = 0; p < 4; ++p) dev_free(f->ctx, f->U[p], f->stream);
   delete f;
   return DW_OK;
 }

@@ -1,0 +1,265 @@
+// Serving loop: continuous batching of solve requests (see dwsap.h).
+//
+// Requests wait in a FIFO queue. A slot admits the head of the queue as soon
+// as the request's device-memory footprint fits the budget beside the
+// requests already running; the slot then imports the gauge field and runs
+// the lock-step FGMRES-DR solve on its own HIP stream, so admitted requests
+// overlap on the device. Server allocations are stream-ordered
+// (hipMallocAsync / hipFreeAsync on the slot's stream).
+#include <string.h>
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "dw_internal.hpp"
+
+namespace dw {
+size_t solver_bytes(long long sites, int m, int prec, int nrhs);
+}
+
+using namespace dw;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void* async_alloc(size_t bytes, hipStream_t s, void*) {
+  void* p = nullptr;
+  if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
+  return p;
+}
+void async_free(void* p, hipStream_t s, void*) { (void)hipFreeAsync(p, s); }
+
+struct Req {
+  uint64_t ticket = 0;
+  dw_request r{};
+  size_t footprint = 0;
+  dw_req_state state = DW_REQ_QUEUED;
+  std::vector<dw_solve_stats> stats;
+  std::string err;
+  double t_submit = 0, t_start = 0, t_end = 0;
+};
+
+}  // namespace
+
+struct dw_server_s {
+  dw_ctx user_ctx = nullptr;
+  dw_ctx ictx = nullptr;  // stream-ordered allocator
+  dw_server_params p{};
+  double budget = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<Req>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
+  double in_use = 0;
+  bool stop = false;
+  uint64_t next = 1;
+  std::vector<std::thread> workers;
+};
+
+namespace {
+
+void worker(dw_server s) {
+  (void)hipSetDevice(s->ictx->device);
+  hipStream_t st = nullptr;
+  const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  while (true) {
+    std::shared_ptr<Req> rq;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      // FIFO admission: the head runs once its footprint fits beside the
+      // running requests. It always fits once none run (submit checked it
+      // against the whole budget), so the queue drains even after stop.
+      s->cv.wait(lk, [&] {
+        if (!s->queue.empty()) return s->in_use + (double)s->queue.front()->footprint <= s->budget;
+        return s->stop;
+      });
+      if (s->queue.empty()) break;
+      rq = s->queue.front();
+      s->queue.pop_front();
+      s->in_use += (double)rq->footprint;
+      rq->state = DW_REQ_RUNNING;
+      rq->t_start = now_s();
+    }
+    dw_status status = have_stream ? DW_OK : DW_EHIP;
+    std::string err = have_stream ? "" : "could not create a stream for the server slot";
+    if (status == DW_OK) {
+      dw_field f = nullptr;
+      status = dw_field_create(s->ictx, rq->r.L, rq->r.block, rq->r.U, st, &f);
+      if (status == DW_OK) {
+        status = fgmresdr_solve(f, rq->r.m0, &rq->r.params, rq->r.b, rq->r.x, rq->r.nrhs, rq->stats.data(), st);
+        if (status != DW_OK && status != DW_ENOTCONV) err = dw_last_error();
+        (void)hipStreamSynchronize(st);
+        dw_field_destroy(f);
+      } else {
+        err = dw_last_error();
+      }
+      (void)hipStreamSynchronize(st);
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->in_use -= (double)rq->footprint;
+      rq->t_end = now_s();
+      rq->state = (status == DW_OK || status == DW_ENOTCONV) ? DW_REQ_DONE : DW_REQ_FAILED;
+      rq->err = err;
+    }
+    s->cv.notify_all();
+  }
+  if (have_stream) (void)hipStreamDestroy(st);
+}
+
+bool valid_geom(const dw_request* q, Geom* g) {
+  int L[4] = {q->L[0], q->L[1], q->L[2], q->L[3]}, B[4] = {q->block[0], q->block[1], q->block[2], q->block[3]};
+  return make_geom(L, B, g) == nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dw_request_footprint(const dw_request* q) {
+  Geom g;
+  if (!q || q->nrhs < 1 || !valid_geom(q, &g)) return 0;
+  const int prec = q->params.sap.storage;
+  if (prec < 0 || prec > 3 || q->params.m < 1 || q->params.m > 48) return 0;
+  const size_t links = (size_t)g.V * 36 * (16 + 8 + 4 + 4);
+  return links + solver_bytes(g.V, q->params.m, prec, q->nrhs);
+}
+
+dw_status dw_server_create(dw_ctx ctx, const dw_server_params* p, dw_server* out) {
+  clear_error();
+  if (!ctx || !p || !out || p->slots < 1 || p->queue_capacity < 1 || p->budget_bytes < 0) {
+    set_error("dw_server_create: invalid argument");
+    return DW_EINVAL;
+  }
+  *out = nullptr;
+  DW_CHECK_HIP(hipSetDevice(ctx->device));
+  dw_allocator a{async_alloc, async_free, nullptr};
+  dw_ctx ictx = nullptr;
+  DW_TRY(dw_ctx_create(ctx->device, &a, &ictx));
+  dw_server s = new dw_server_s;
+  s->user_ctx = ctx;
+  s->ictx = ictx;
+  s->p = *p;
+  if (p->budget_bytes > 0) {
+    s->budget = p->budget_bytes;
+  } else {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      dw_ctx_destroy(ictx);
+      delete s;
+      set_error("dw_server_create: hipMemGetInfo failed");
+      return DW_EHIP;
+    }
+    s->budget = 0.8 * (double)fr;
+  }
+  for (int i = 0; i < p->slots; ++i) s->workers.emplace_back(worker, s);
+  *out = s;
+  return DW_OK;
+}
+
+dw_status dw_server_destroy(dw_server s) {
+  clear_error();
+  if (!s) return DW_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& t : s->workers) t.join();
+  dw_ctx_destroy(s->ictx);
+  delete s;
+  return DW_OK;
+}
+
+dw_status solve_submit(dw_server s, const dw_request* q, uint64_t* ticket) {
+  clear_error();
+  if (!s || !q || !ticket || !q->U || !q->b || !q->x || q->nrhs < 1) {
+    set_error("solve_submit: invalid argument");
+    return DW_EINVAL;
+  }
+  Geom g;
+  if (!valid_geom(q, &g)) {
+    set_error("solve_submit: invalid lattice / block geometry");
+    return DW_EINVAL;
+  }
+  for (int mu = 0; mu < 4; ++mu)
+    if (q->params.sap.block[mu] != q->block[mu]) {
+      set_error("solve_submit: params.sap.block differs from the request's block");
+      return DW_EINVAL;
+    }
+  const fgmresdr_params& P = q->params;
+  if (P.m < 1 || P.m > 48 || P.k < 0 || P.k >= P.m || P.k > 23 || P.max_iter < 1 || !(P.tol > 0) ||
+      !(P.restart_t > 0) || P.sap.ncycles < 1 || P.sap.nmr < 0 || P.sap.storage < 0 || P.sap.storage > 3) {
+    set_error("solve_submit: invalid solver parameters");
+    return DW_EINVAL;
+  }
+  const size_t fp = dw_request_footprint(q);
+  auto rq = std::make_shared<Req>();
+  rq->r = *q;
+  rq->footprint = fp;
+  rq->stats.resize(q->nrhs);
+  rq->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if ((double)fp > s->budget) {
+      set_error("solve_submit: request needs %zu bytes, above the server budget %.0f", fp, s->budget);
+      return DW_EINVAL;
+    }
+    if ((int)s->queue.size() >= s->p.queue_capacity) {
+      set_error("solve_submit: queue full (%d requests)", s->p.queue_capacity);
+      return DW_EBUSY;
+    }
+    rq->ticket = s->next++;
+    s->queue.push_back(rq);
+    s->reqs[rq->ticket] = rq;
+    *ticket = rq->ticket;
+  }
+  s->cv.notify_all();
+  return DW_OK;
+}
+
+dw_status solve_poll(dw_server s, uint64_t ticket, dw_req_state* state, dw_solve_stats* stats,
+                     dw_request_times* times) {
+  clear_error();
+  if (!s || !state) {
+    set_error("solve_poll: invalid argument");
+    return DW_EINVAL;
+  }
+  std::shared_ptr<Req> rq;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) {
+      set_error("solve_poll: unknown ticket %llu", (unsigned long long)ticket);
+      return DW_ENOTFOUND;
+    }
+    rq = it->second;
+    *state = rq->state;
+    if (rq->state == DW_REQ_DONE || rq->state == DW_REQ_FAILED) s->reqs.erase(it);
+  }
+  if (*state == DW_REQ_DONE || *state == DW_REQ_FAILED) {
+    if (stats) memcpy(stats, rq->stats.data(), rq->stats.size() * sizeof(dw_solve_stats));
+    if (times) {
+      times->queued = rq->t_start - rq->t_submit;
+      times->running = rq->t_end - rq->t_start;
+      times->latency = rq->t_end - rq->t_submit;
+    }
+    if (*state == DW_REQ_FAILED) set_error("%s", rq->err.c_str());
+  }
+  return DW_OK;
+}
+
+}  // extern "C"

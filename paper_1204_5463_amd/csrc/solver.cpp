@@ -324,6 +324,12 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
 
 }  // namespace
 
+namespace dw {
+size_t solver_bytes(long long sites, int m, int prec, int nrhs) {
+  return bytes_per_rhs(sites * 12, m, prec) * (size_t)nrhs + (size_t)nrhs * 64 * 1024;
+}
+}  // namespace dw
+
 extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params* P, const double* b, double* x,
                                     int32_t nrhs, dw_solve_stats* stats, hipStream_t stream) {
   clear_error();

@@ -43,3 +43,29 @@ def test_binding_fails_loudly_without_library(tmp_path):
         P._lib = None
         P.load(str(tmp_path / "nope.so"))
     P._lib = None
+
+
+def test_request_footprint_host_logic():
+    """dw_request_footprint is host arithmetic: links + per-RHS solver memory, linear in nrhs."""
+    import ctypes
+
+    import paper_1204_5463_amd as P
+
+    def fp(L=(8, 8, 8, 8), block=(4, 4, 4, 4), nrhs=1, m=20, k=5, prec=P.DW_PREC_F16):
+        r = P._Request()
+        for i in range(4):
+            r.L[i], r.block[i] = L[i], block[i]
+        r.nrhs = nrhs
+        r.params = P.SolverParams(m=m, k=k, sap=P.SapParams(block=block, storage=prec))._c()
+        return int(P.lib().dw_request_footprint(ctypes.byref(r)))
+
+    V = 8 ** 4
+    f1, f2, f3 = fp(nrhs=1), fp(nrhs=2), fp(nrhs=3)
+    per = f2 - f1
+    assert per > 0 and f3 - f2 == per
+    links = f1 - per
+    assert links == V * 36 * (16 + 8 + 4 + 4)
+    # the Krylov bases dominate the per-RHS part: (m+1) V and m Z columns in FP64
+    assert per >= V * 12 * 16 * (21 + 20)
+    assert fp(m=30, k=5) > f1
+    assert fp(block=(3, 4, 4, 4)) == 0 and fp(nrhs=0) == 0 and fp(m=49) == 0
