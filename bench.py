@@ -38,7 +38,20 @@ WORKLOADS = {
                     block=(4, 4, 4, 4), ncycles=2, nmr=5, storage="f32", m=30, k=10),
     "8^4": dict(L=(8, 8, 8, 8), eps=0.3, seed=0, mass=(None, -0.1),
                 block=(4, 4, 4, 4), ncycles=1, nmr=4, storage="f16", m=20, k=5),
+    # 12 point-source + noise RHS in lock-step (one SAP / operator launch for
+    # all of them); m, k reduced from (30, 12) so that the 12 FP64 Krylov
+    # bases fit in one GPU's memory
+    "32^3x64x12": dict(L=(32, 32, 32, 64), eps=0.7, seed=0, mass=(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
+                       block=(8, 4, 4, 4), ncycles=2, nmr=5, storage="f16", m=20, k=8, nrhs=12, rhs="point"),
+    "48^3x96": dict(L=(48, 48, 48, 96), eps=0.7, seed=0, mass=(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
+                    block=(8, 4, 4, 4), ncycles=2, nmr=5, storage="f16", m=30, k=12),
 }
+
+# serving stream: lattice sizes of the request mix (eps 0.6 links, gauge seed 0)
+SERVE_LATTICES = {"8^4": (8, 8, 8, 8), "16^3x32": (16, 16, 16, 32), "24^3x48": (24, 24, 24, 48),
+                  "32^3x64": (32, 32, 32, 64)}
+SERVE_MASS = {"8^4": ("8^4_eps0.6",), "16^3x32": ("16^3x32_eps0.6", "12^4_eps0.6"),
+              "24^3x48": ("16^3x32_eps0.6", "12^4_eps0.6"), "32^3x64": ("16^3x32_eps0.6", "12^4_eps0.6")}
 
 
 def log(*a):
@@ -171,6 +184,145 @@ def cpu_baseline(L, eps, seed, m0, wl, iterations, cycles):
     }
 
 
+def solver_params(P, wl, prec, tuned=None):
+    if tuned is not None:
+        return tuned
+    sap = P.SapParams(block=wl["block"], ncycles=wl["ncycles"], nmr=wl["nmr"], storage=prec)
+    return P.SolverParams(m=wl["m"], k=wl["k"], tol=1e-10, restart_t=5.0, max_iter=20000, sap=sap)
+
+
+def describe(params, P):
+    inv = {v: k for k, v in P.PREC_NAMES.items()}
+    sp = params.sap
+    return (f"SAP {inv[sp.storage]} storage {'x'.join(map(str, sp.block))} blocks s={sp.ncycles} nMR={sp.nmr}, "
+            f"FGMRES-DR({params.m},{params.k}) FP64 outer, tol {params.tol:g}")
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, max(0, int(math.ceil(q * len(xs))) - 1))]
+
+
+def serve(args):
+    """Serving stream: exponential inter-arrivals, a mix of lattice sizes
+    and RHS counts near the critical mass, solved by the library's server
+    (continuous batching on concurrent streams, FP16 SAP) and, for
+    comparison, one request at a time with all-FP64 SAP in the same order
+    (its latencies follow from the measured service times and the same
+    arrival times). Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_1204_5463_amd as P
+    import synth
+
+    rng = np.random.default_rng(20)
+    names = sorted(SERVE_LATTICES, key=lambda n: math.prod(SERVE_LATTICES[n]))
+    log(f"[serve] generating gauge fields for {names}")
+    fields = {n: P.to_device(synth.gauge_field(SERVE_LATTICES[n], 0.6, 0)) for n in names}
+    mc = {}
+    with open(os.path.join(ROOT, "tests", "golden", "critical_mass.json")) as fh:
+        crit = json.load(fh)
+    for n in names:
+        src = next(s for s in SERVE_MASS[n] if s in crit)
+        mc[n] = (crit[src]["m_c"], src)
+    reqs, t = [], 0.0
+    for i in range(args.requests):
+        t += rng.exponential(args.mean_gap)
+        n = names[int(rng.integers(len(names)))]
+        nrhs = int(rng.integers(1, args.max_rhs + 1))
+        delta = float(np.exp(rng.uniform(np.log(2e-3), np.log(2e-2))))
+        reqs.append(dict(arrival=t, lattice=n, nrhs=nrhs, m0=mc[n][0] + delta, seed=3000 + 100 * i))
+    for r in reqs:
+        r["b"] = P.to_device(synth.gaussian_spinors(SERVE_LATTICES[r["lattice"]], r["nrhs"], seed0=r["seed"]))
+    log(f"[serve] {len(reqs)} requests over {t:.2f} s of arrivals")
+
+    def params(storage):
+        return P.SolverParams(m=30, k=12, tol=1e-10, restart_t=5.0, max_iter=20000,
+                              sap=P.SapParams(block=(4, 4, 4, 4), ncycles=2, nmr=5, storage=storage))
+
+    ctx = P.Context(0)
+    # warm the kernels of every lattice once (untimed)
+    for n in names:
+        L = SERVE_LATTICES[n]
+        f = P.Field(ctx, L, (4, 4, 4, 4), fields[n])
+        f.solve(mc[n][0] + 0.05, params(P.DW_PREC_F16), P.to_device(synth.gaussian_spinors(L, 1, seed0=1)),
+                raise_on_notconv=False)
+        f.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    srv = P.Server(ctx, slots=args.slots, queue_capacity=len(reqs))
+    pending, done = {}, {}
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i]["arrival"] <= now:
+            r = reqs[i]
+            tk = srv.submit(SERVE_LATTICES[r["lattice"]], (4, 4, 4, 4), r["m0"], fields[r["lattice"]], r["b"],
+                            params(P.DW_PREC_F16))
+            pending[tk] = i
+            i += 1
+        for tk in list(pending):
+            out = srv.poll(tk)
+            if out is not None:
+                x, st, tm = out
+                k = pending.pop(tk)
+                done[k] = (st, tm, time.perf_counter() - t0)
+                r = reqs[k]
+                log(f"[serve] request {k} {r['lattice']} nrhs={r['nrhs']} done: "
+                    f"{max(s.iterations for s in st)} it, latency {tm['latency']:.3f} s")
+                del x
+        time.sleep(2e-4)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    lat = [done[k][1]["latency"] for k in range(len(reqs))]
+    conv = all(s.converged for k in range(len(reqs)) for s in done[k][0])
+    rhs_total = sum(r["nrhs"] for r in reqs)
+
+    # serial all-FP64 baseline: same order, one request at a time
+    log("[serve] serial FP64 baseline")
+    svc = []
+    for k, r in enumerate(reqs):
+        L = SERVE_LATTICES[r["lattice"]]
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        f = P.Field(ctx, L, (4, 4, 4, 4), fields[r["lattice"]])
+        _, st = f.solve(r["m0"], params(P.DW_PREC_F64), r["b"], raise_on_notconv=False)
+        f.close()
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - ts)
+        log(f"[serve] serial {k}: {svc[-1]:.3f} s")
+    fin, lat64 = 0.0, []
+    for r, sv in zip(reqs, svc):
+        fin = max(fin, r["arrival"]) + sv
+        lat64.append(fin - r["arrival"])
+    line = {
+        "metric": "serving throughput (requests/s) of a Poisson stream of solve requests, continuous batching",
+        "value": round(len(reqs) / makespan, 4),
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, exponential gaps mean {args.mean_gap * 1e3:.0f} ms (seed 20), "
+                               f"lattices {names} uniform, nrhs 1..{args.max_rhs}, eps=0.6 links, "
+                               f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s=2 nMR=5, FGMRES-DR(30,12), tol 1e-10, "
+                               f"{args.slots} slots",
+                   "m_c_from": {n: mc[n][1] for n in names}},
+        "makespan_s": round(makespan, 3),
+        "rhs_solves_per_s": round(rhs_total / makespan, 4),
+        "p50_latency_ms": round(1e3 * pct(lat, 0.5), 1),
+        "p99_latency_ms": round(1e3 * pct(lat, 0.99), 1),
+        "all_converged": conv,
+        "serial_fp64": {"requests_per_s": round(len(reqs) / fin, 4) if fin > 0 else None,
+                        "busy_s": round(sum(svc), 3),
+                        "p50_latency_ms": round(1e3 * pct(lat64, 0.5), 1),
+                        "p99_latency_ms": round(1e3 * pct(lat64, 0.99), 1)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,11 +333,23 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--skip-dslash", action="store_true", help="skip the per-precision operator timings")
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
+    ap.add_argument("--also-k0", action="store_true", help="also run FGMRES(m) (k = 0) on the same system")
+    ap.add_argument("--sequential", action="store_true",
+                    help="multi-RHS workloads: also time the RHS one after another")
+    ap.add_argument("--autotune", default=None, metavar="CACHE.json",
+                    help="tune (block, nMR, s, m, k) by time to solution before timing (cached in this file)")
+    ap.add_argument("--serve", action="store_true", help="run the serving stream instead of the solve benchmark")
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
+    ap.add_argument("--max-rhs", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU volume split is a design, not built", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve(args)
 
     import numpy as np
     import torch
@@ -203,18 +367,38 @@ def main():
     log(f"[bench] workload {args.workload}: L={L} eps={wl['eps']} m0={m0:.6f}; generating inputs")
     t0 = time.time()
     U = synth.gauge_field(L, wl["eps"], wl["seed"])
-    b = synth.gaussian_spinor(L, 1000)
+    nrhs = wl.get("nrhs", 1)
+    if wl.get("rhs") == "point":
+        b = np.stack([synth.point_source_noise(L, j, 1000 + j) for j in range(nrhs)])
+    else:
+        b = synth.gaussian_spinors(L, nrhs, seed0=1000)
     log(f"[bench] inputs ready in {time.time() - t0:.1f} s")
     ctx = P.Context(0)
-    f = P.Field(ctx, L, wl["block"], P.to_device(U))
+    Ud = P.to_device(U)
     del U
     bt = P.to_device(b)
-    sap = P.SapParams(block=wl["block"], ncycles=wl["ncycles"], nmr=wl["nmr"], storage=prec)
-    params = P.SolverParams(m=wl["m"], k=wl["k"], tol=1e-10, restart_t=5.0, max_iter=20000, sap=sap)
+    params = solver_params(P, wl, prec)
+    tune = None
+    if args.autotune:
+        log("[bench] autotuning (untimed)")
+        ts = time.perf_counter()
+        space = P.TuneSpace(nmr=(3, 7), s=(1, 3), mk=((wl["m"], wl["k"] // 2), (wl["m"] - 6, wl["k"] - 4)),
+                            iter_cap=2.0)
+        params, trials = P.autotune(ctx, L, Ud, m0, params, bt, space=space, cache=P.TuneCache(args.autotune))
+        for t in trials:
+            log(f"[bench]   trial {t}")
+        tune = {"trials": len(trials), "tuning_s": round(time.perf_counter() - ts, 1)}
+        torch.cuda.empty_cache()
+    f = P.Field(ctx, L, params.sap.block, Ud)
+    del Ud
+
+    def summary(st):
+        return (f"{max(s.iterations for s in st)} it, relres <= {max(s.true_relres for s in st):.2e}, "
+                f"converged {all(s.converged for s in st)}")
 
     for i in range(args.warmup):
         _, st = f.solve(m0, params, bt)
-        log(f"[bench] warmup solve {i}: {st[0].iterations} it, {st[0].seconds:.3f} s, relres {st[0].true_relres:.2e}")
+        log(f"[bench] warmup solve {i}: {summary(st)}, {st[0].seconds:.3f} s")
 
     # ---- timed region: K complete solves
     ctx.profile_reset()
@@ -226,18 +410,21 @@ def main():
         ts = time.perf_counter()
         x, st = f.solve(m0, params, bt)
         lat.append(time.perf_counter() - ts)
-        stats.append(st[0])
-        log(f"[bench] solve {i}: {st[0].iterations} it, {lat[-1]:.3f} s, relres {st[0].true_relres:.2e}")
+        stats.append(st)
+        log(f"[bench] solve {i}: {summary(st)}, {lat[-1]:.3f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ctx.profile(False)
     kern = ctx.profile_stats()
-    value = args.steps / elapsed
-    st0 = stats[-1]
+    value = nrhs * args.steps / elapsed
+    stl = stats[-1]
+    st0 = max(stl, key=lambda s: s.iterations)
 
-    # independent FP64 residual check of the last solution (library FP64 operator)
-    r = bt - f.apply(m0, x)
-    relres_check = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(bt))
+    # independent FP64 residual check of the last solutions (library FP64 operator)
+    relres_check = 0.0
+    for j in range(nrhs):
+        r = bt[j] - f.apply(m0, x[j].contiguous())
+        relres_check = max(relres_check, float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(bt[j])))
     del r
 
     # dominant kernel class in the timed region
@@ -267,19 +454,55 @@ def main():
                       "TFLOP/s": round(v["flops"] / v["ms"] / 1e9, 2) if v["ms"] > 0 and v["flops"] else None}
 
     out_extra = {}
+    if tune is not None:
+        out_extra["autotune"] = tune
+    del x
     # ---- all-FP64 comparison solve
     if not args.skip_fp64:
-        p64 = P.SolverParams(m=wl["m"], k=wl["k"], tol=1e-10, restart_t=5.0, max_iter=20000,
-                             sap=P.SapParams(block=wl["block"], ncycles=wl["ncycles"], nmr=wl["nmr"],
+        p64 = P.SolverParams(m=params.m, k=params.k, tol=params.tol, restart_t=params.restart_t,
+                             max_iter=params.max_iter,
+                             sap=P.SapParams(block=params.sap.block, ncycles=params.sap.ncycles, nmr=params.sap.nmr,
                                              storage=P.DW_PREC_F64))
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         ts = time.perf_counter()
         _, s64 = f.solve(m0, p64, bt)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - ts
-        log(f"[bench] FP64 solve: {s64[0].iterations} it, {t64:.3f} s, relres {s64[0].true_relres:.2e}")
-        out_extra.update({"fp64_solves_per_s": round(1.0 / t64, 4), "fp64_iterations": s64[0].iterations,
-                          "speedup_vs_fp64": round(value * t64, 3)})
+        log(f"[bench] FP64 solve: {summary(s64)}, {t64:.3f} s")
+        out_extra.update({"fp64_solves_per_s": round(nrhs / t64, 4),
+                          "fp64_iterations": max(s.iterations for s in s64),
+                          "speedup_vs_fp64": round(value * t64 / nrhs, 3)})
+    # ---- FGMRES(m): the same solve without deflation
+    if args.also_k0:
+        pk0 = P.SolverParams(m=params.m, k=0, tol=params.tol, restart_t=params.restart_t,
+                             max_iter=max(4 * st0.iterations, 2000), sap=params.sap)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        ts = time.perf_counter()
+        _, sk0 = f.solve(m0, pk0, bt, raise_on_notconv=False)
+        torch.cuda.synchronize()
+        tk0 = time.perf_counter() - ts
+        log(f"[bench] FGMRES({params.m}) solve: {summary(sk0)}, {tk0:.3f} s")
+        out_extra["fgmres_k0"] = {"iterations": max(s.iterations for s in sk0),
+                                  "converged": all(s.converged for s in sk0),
+                                  "relres": max(s.true_relres for s in sk0), "seconds": round(tk0, 3),
+                                  "max_iter": pk0.max_iter}
+    # ---- the RHS one after another (multi-RHS workloads)
+    if args.sequential and nrhs > 1:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        its = []
+        for j in range(nrhs):
+            _, sj = f.solve(m0, params, bt[j:j + 1].contiguous())
+            its.append(sj[0].iterations)
+        torch.cuda.synchronize()
+        tseq = time.perf_counter() - ts
+        log(f"[bench] {nrhs} sequential solves: {tseq:.3f} s")
+        out_extra["sequential"] = {"rhs_solves_per_s": round(nrhs / tseq, 4), "iterations": its,
+                                   "lockstep_speedup": round(value * tseq / nrhs, 3)}
+    if nrhs > 1:
+        out_extra["iterations_per_rhs"] = [s.iterations for s in stl]
 
     # ---- Wilson-Dirac operator alone, each storage precision
     if not args.skip_dslash:
@@ -299,13 +522,15 @@ def main():
     if not args.skip_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(L, wl["eps"], wl["seed"], m0, wl, st0.iterations, st0.cycles)
+        if nrhs > 1:
+            cpu["unit"] = "RHS solves/s"  # the oracle solves the RHS one after another
 
     lat_ms = sorted(1000 * t for t in lat)
     line = {
         "metric": "solves/s to 1e-10 true residual, mixed-precision SAP+FGMRES-DR (Dslash HBM GB/s and "
                   "all-FP64 GPU solver alongside)",
         "value": round(value, 4),
-        "unit": "solves/s",
+        "unit": "solves/s" if nrhs == 1 else "RHS solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -316,10 +541,11 @@ def main():
         "dtype": "f32+f64" if prec != P.DW_PREC_F64 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload} lattice, eps={wl['eps']} SU(3) links (seed 0), m0={m0:.6f} "
-                               f"near-critical, Gaussian RHS, SAP {wl['storage']} storage "
-                               f"{'x'.join(map(str, wl['block']))} blocks s={wl['ncycles']} nMR={wl['nmr']}, "
-                               f"FGMRES-DR({wl['m']},{wl['k']}) FP64 outer, tol 1e-10",
-                   "lattice": list(L), "m0": m0, "m0_from": mass_src, "sap_storage": wl["storage"],
+                               f"near-critical, "
+                               + (f"{nrhs} point-source+noise RHS in lock-step, " if wl.get("rhs") == "point"
+                                  else f"{nrhs} Gaussian RHS, ")
+                               + describe(params, P) + (" (autotuned)" if tune is not None else ""),
+                   "lattice": list(L), "m0": m0, "m0_from": mass_src, "sap_storage": wl["storage"], "nrhs": nrhs,
                    "parallelism": "single GPU"},
         "iterations": st0.iterations,
         "cycles": st0.cycles,

@@ -95,8 +95,8 @@ typedef struct sap_params {
  *   restart_t  clean restart (no deflation) when ||r_explicit|| / ||r_implicit||
  *              exceeds this threshold (the paper suggests 2..10).
  *   sap        preconditioner parameters.
- *   shared_defl  multi-RHS only: 1 = project every RHS's restart residual
- *              onto the deflation space of RHS 0 (see fgmresdr_solve).
+ *   shared_defl  must be 0 (a shared multi-RHS deflation space is not
+ *              provided; every RHS deflates with its own harmonic Ritz vectors).
  *   flags      reserved, pass 0. */
 typedef struct fgmresdr_params {
   int32_t m;
@@ -172,8 +172,8 @@ dw_status sap_precondition(dw_field field, double m0, const sap_params* sap, con
  * is computed in FP64 once per cycle and enters the least-squares right-hand
  * side (Section 4.7); the preconditioner runs at `params->sap.storage`.
  * b, x: canonical spinor arrays (nrhs each). stats: host array of nrhs
- * entries (may be NULL). Synchronises `stream` once per cycle and before
- * returning. Returns DW_ENOTCONV if any RHS stopped at max_iter (x then
+ * entries (may be NULL). Synchronises `stream` once per Arnoldi step (to
+ * read the step's residual and breakdown scalars) and before returning. Returns DW_ENOTCONV if any RHS stopped at max_iter (x then
  * holds its last iterate and stats are filled). */
 dw_status fgmresdr_solve(dw_field field, double m0, const fgmresdr_params* params, const double* b, double* x,
                          int32_t nrhs, dw_solve_stats* stats, hipStream_t stream);
@@ -234,6 +234,45 @@ dw_status solve_submit(dw_server server, const dw_request* req, uint64_t* ticket
  * returned by dw_last_error() of the polling thread. */
 dw_status solve_poll(dw_server server, uint64_t ticket, dw_req_state* state, dw_solve_stats* stats,
                      dw_request_times* times);
+
+/* ---- autotuner -------------------------------------------------------------
+ * The paper fixes the SAP parameters by hardware efficiency and then tunes
+ * m and k (Section 5). Because the block shape, the MR step count and the
+ * cycle count s change the iteration count as well as the cost per
+ * iteration, the tuner's objective is the wall-clock time of the whole
+ * solve to the requested tolerance. It searches coordinate-wise from
+ * `base`: block shape, then nmr, then s, then (m, k), keeping the best so
+ * far each time; a candidate's max_iter is capped at `iter_cap` times the
+ * best iteration count so far, so hopeless candidates stop early. */
+typedef struct dw_tune_space {
+  int32_t nblocks;        /* candidate block shapes in blocks[]; 0 = every shape with extents in
+                           * {2, 4, 8}, volume 128..512, longest <= 2 x shortest extent, valid for L */
+  int32_t blocks[16][4];
+  int32_t nmr_min, nmr_max;  /* MR steps searched (inclusive); nmr_max < nmr_min: keep base */
+  int32_t s_min, s_max;      /* SAP cycles searched (inclusive); s_max < s_min: keep base */
+  int32_t nmk;               /* (m, k) candidates in mk[] (0: keep base) */
+  int32_t mk[8][2];
+  int32_t repeats;           /* timed solves per candidate, the fastest counts (>= 1) */
+  double iter_cap;           /* max_iter of a candidate = iter_cap * best iterations (<= 0: base max_iter) */
+} dw_tune_space;
+
+typedef struct dw_tune_trial {
+  fgmresdr_params params;  /* the candidate */
+  int32_t converged;       /* every RHS reached tol */
+  int32_t iterations;      /* largest iteration count over the RHS */
+  double seconds;          /* fastest wall-clock time of the whole solve */
+} dw_tune_trial;
+
+/* Tunes the solver for lattice L, gauge field U (canonical layout, device),
+ * mass m0 and right-hand sides b (nrhs canonical spinors, device). x is a
+ * device work array of the size of b (it holds the last candidate's
+ * solution). trials: host array of max_trials entries receiving every
+ * candidate in the order tried; *ntrials is set to the count. *best gets
+ * the fastest converged candidate (DW_ENOTCONV if none converged). Fields
+ * for the candidate block shapes are created and destroyed inside. */
+dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U, double m0, const fgmresdr_params* base,
+                      const dw_tune_space* space, const double* b, double* x, int32_t nrhs, dw_tune_trial* trials,
+                      int32_t max_trials, int32_t* ntrials, fgmresdr_params* best, hipStream_t stream);
 
 /* ---- per-kernel-class timing ---------------------------------------------
  * When enabled on a context, every kernel launch made for that context is

@@ -23,6 +23,7 @@ import torch
 __all__ = [
     "DW_PREC_F64", "DW_PREC_F32", "DW_PREC_F16", "DW_PREC_BF16", "PREC_NAMES",
     "DwError", "NotConverged", "Context", "Field", "SapParams", "SolverParams", "SolveStats", "Server",
+    "TuneSpace", "TuneCache", "autotune",
     "lib", "load",
 ]
 
@@ -86,6 +87,19 @@ class _ReqTimes(ctypes.Structure):
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+class _TuneSpace(ctypes.Structure):
+    _fields_ = [("nblocks", ctypes.c_int32), ("blocks", (ctypes.c_int32 * 4) * 16),
+                ("nmr_min", ctypes.c_int32), ("nmr_max", ctypes.c_int32),
+                ("s_min", ctypes.c_int32), ("s_max", ctypes.c_int32),
+                ("nmk", ctypes.c_int32), ("mk", (ctypes.c_int32 * 2) * 8),
+                ("repeats", ctypes.c_int32), ("iter_cap", ctypes.c_double)]
+
+
+class _TuneTrial(ctypes.Structure):
+    _fields_ = [("params", _SolverParams), ("converged", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("seconds", ctypes.c_double)]
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -177,6 +191,9 @@ def load(path: str = LIB_PATH):
         "solve_submit": (st, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
         "solve_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(_Stats),
                             ctypes.POINTER(_ReqTimes)]),
+        "dw_autotune": (st, [vp, ctypes.POINTER(i32), vp, dbl, ctypes.POINTER(_SolverParams),
+                             ctypes.POINTER(_TuneSpace), vp, vp, i32, ctypes.POINTER(_TuneTrial), i32,
+                             ctypes.POINTER(i32), ctypes.POINTER(_SolverParams), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -447,6 +464,119 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+@dataclasses.dataclass
+class TuneSpace:
+    """Search space of dw_autotune: block shapes (empty = the library's default
+    set), MR steps and SAP cycles (inclusive ranges), (m, k) pairs."""
+    blocks: tuple = ()
+    nmr: tuple = (2, 8)
+    s: tuple = (1, 4)
+    mk: tuple = ()
+    repeats: int = 1
+    iter_cap: float = 3.0
+
+    def _c(self):
+        t = _TuneSpace()
+        if len(self.blocks) > 16 or len(self.mk) > 8:
+            raise ValueError("at most 16 block shapes and 8 (m, k) pairs")
+        t.nblocks = len(self.blocks)
+        for i, B in enumerate(self.blocks):
+            for j in range(4):
+                t.blocks[i][j] = int(B[j])
+        t.nmr_min, t.nmr_max = int(self.nmr[0]), int(self.nmr[1])
+        t.s_min, t.s_max = int(self.s[0]), int(self.s[1])
+        t.nmk = len(self.mk)
+        for i, (m, k) in enumerate(self.mk):
+            t.mk[i][0], t.mk[i][1] = int(m), int(k)
+        t.repeats, t.iter_cap = int(self.repeats), float(self.iter_cap)
+        return t
+
+
+def _params_from_c(p: _SolverParams) -> SolverParams:
+    return SolverParams(m=p.m, k=p.k, max_iter=p.max_iter, tol=p.tol, restart_t=p.restart_t,
+                        sap=SapParams(block=tuple(p.sap.block), ncycles=p.sap.ncycles, nmr=p.sap.nmr,
+                                      storage=p.sap.storage), shared_defl=p.shared_defl)
+
+
+class TuneCache:
+    """JSON file of tuned solver parameters, keyed by device architecture,
+    lattice, mass, storage precision, RHS count and tolerance."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    @staticmethod
+    def key(arch, L, m0, base: SolverParams, nrhs):
+        return (f"{arch}|L={'x'.join(str(int(v)) for v in L)}|m0={float(m0):.6f}|prec={base.sap.storage}"
+                f"|nrhs={int(nrhs)}|tol={float(base.tol):.3g}")
+
+    def _load(self):
+        import json
+        if not os.path.exists(self.path):
+            return {}
+        with open(self.path) as fh:
+            return json.load(fh)
+
+    def get(self, key):
+        e = self._load().get(key)
+        if e is None:
+            return None
+        p = e["params"]
+        return SolverParams(m=p["m"], k=p["k"], max_iter=p["max_iter"], tol=p["tol"], restart_t=p["restart_t"],
+                            sap=SapParams(block=tuple(p["block"]), ncycles=p["ncycles"], nmr=p["nmr"],
+                                          storage=p["storage"]))
+
+    def put(self, key, params: SolverParams, trials=()):
+        import json
+        d = self._load()
+        d[key] = {"params": {"m": params.m, "k": params.k, "max_iter": params.max_iter, "tol": params.tol,
+                             "restart_t": params.restart_t, "block": list(params.sap.block),
+                             "ncycles": params.sap.ncycles, "nmr": params.sap.nmr, "storage": params.sap.storage},
+                  "trials": [dict(t) for t in trials]}
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(d, fh, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def autotune(ctx: Context, L, U: torch.Tensor, m0: float, base: SolverParams, b: torch.Tensor,
+             space: TuneSpace | None = None, cache: TuneCache | None = None, max_trials: int = 64, stream=None):
+    """Tune (block, nmr, s, m, k) by time to solution (dw_autotune). Returns
+    (best SolverParams, list of trial dicts); with a cache, a stored result is
+    returned without solving (trials then empty)."""
+    space = space or TuneSpace()
+    vol12 = int(L[0]) * int(L[1]) * int(L[2]) * int(L[3]) * 12
+    nrhs = b.numel() // vol12
+    if nrhs * vol12 != b.numel() or nrhs < 1:
+        raise ValueError("b must hold a whole number of spinor fields of the lattice")
+    key = None
+    if cache is not None:
+        arch = torch.cuda.get_device_properties(b.device).gcnArchName
+        key = TuneCache.key(arch, L, m0, base, nrhs)
+        hit = cache.get(key)
+        if hit is not None:
+            return hit, []
+    La = (ctypes.c_int32 * 4)(*(int(v) for v in L))
+    x = torch.empty_like(b)
+    tr = (_TuneTrial * int(max_trials))()
+    nt = ctypes.c_int32()
+    best = _SolverParams()
+    bp, sp = base._c(), space._c()
+    _check(lib().dw_autotune(ctx.handle, La, _dev_ptr(U), float(m0), ctypes.byref(bp), ctypes.byref(sp),
+                             _dev_ptr(b), _dev_ptr(x), nrhs, tr, int(max_trials), ctypes.byref(nt),
+                             ctypes.byref(best), _stream(stream)), "dw_autotune")
+    trials = []
+    for t in tr[:nt.value]:
+        p = t.params
+        trials.append({"block": list(p.sap.block), "nmr": p.sap.nmr, "ncycles": p.sap.ncycles, "m": p.m,
+                       "k": p.k, "converged": bool(t.converged), "iterations": t.iterations,
+                       "seconds": t.seconds})
+    bestp = _params_from_c(best)
+    if cache is not None:
+        cache.put(key, bestp, trials)
+    return bestp, trials
 
 
 def to_device(a, device="cuda"):

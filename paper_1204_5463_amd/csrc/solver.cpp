@@ -345,6 +345,10 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
     return DW_EINVAL;
   }
   DW_TRY(check_sap_params(f->g, &P->sap));
+  if (P->shared_defl != 0) {
+    set_error("fgmresdr_solve: shared_defl must be 0");
+    return DW_EINVAL;
+  }
   if (P->sap.ncycles < 1) {
     set_error("fgmresdr_solve: need at least one SAP cycle");
     return DW_EINVAL;

@@ -69,3 +69,24 @@ def test_request_footprint_host_logic():
     assert per >= V * 12 * 16 * (21 + 20)
     assert fp(m=30, k=5) > f1
     assert fp(block=(3, 4, 4, 4)) == 0 and fp(nrhs=0) == 0 and fp(m=49) == 0
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    import paper_1204_5463_amd as P
+
+    c = P.TuneCache(str(tmp_path / "t.json"))
+    base = P.SolverParams(m=30, k=12, tol=1e-10, sap=P.SapParams(block=(4, 4, 4, 4), storage=P.DW_PREC_F16))
+    k1 = P.TuneCache.key("gfx950", (32, 32, 32, 64), -1.137, base, 1)
+    k2 = P.TuneCache.key("gfx950", (32, 32, 32, 64), -1.138, base, 1)
+    k3 = P.TuneCache.key("gfx950", (32, 32, 32, 64), -1.137, base, 12)
+    assert len({k1, k2, k3}) == 3
+    assert c.get(k1) is None
+    tuned = P.SolverParams(m=24, k=8, tol=1e-10, sap=P.SapParams(block=(8, 4, 4, 4), ncycles=2, nmr=5,
+                                                                  storage=P.DW_PREC_F16))
+    c.put(k1, tuned, [{"block": [8, 4, 4, 4], "seconds": 1.0}])
+    c.put(k3, base)
+    assert c.get(k1) == tuned and c.get(k3) == base and c.get(k2) is None
+    # the C struct carries every field of the space
+    s = P.TuneSpace(blocks=((4, 4, 4, 4), (8, 4, 4, 4)), nmr=(3, 6), s=(1, 3), mk=((20, 5),), repeats=2)._c()
+    assert s.nblocks == 2 and list(s.blocks[1]) == [8, 4, 4, 4] and (s.nmr_min, s.nmr_max) == (3, 6)
+    assert s.nmk == 1 and list(s.mk[0]) == [20, 5] and s.repeats == 2
