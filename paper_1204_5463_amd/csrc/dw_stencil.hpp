@@ -157,6 +157,103 @@ __device__ __forceinline__ void hop_dispatch(int h, cplx<T> acc[12], PsiF&& psi,
   }
 }
 
+// ---- FP16 / BF16 links --------------------------------------------------
+// With 16-bit links the two half-spinor rows are rounded to the link format
+// (round to nearest even) and every complex product is a pair of two-term
+// dot products of 16-bit operands accumulated in FP32 (v_dot2 on gfx950):
+//   (w h).re = dot((w.re, w.im), (h.re, -h.im)),  (w h).im = dot(w, (h.im, h.re)),
+//   (w* h).re = dot(w, (h.re, h.im)),             (w* h).im = dot(w, (h.im, -h.re)).
+// The products of 16-bit numbers are exact in FP32, so the only extra
+// rounding is that of the half spinor.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+
+template <typename SG>
+struct link16;
+template <>
+struct link16<s16> {
+  using V = h2v;
+  static __device__ __forceinline__ V pk(float a, float b) {
+    V r;
+    r.x = (_Float16)a;
+    r.y = (_Float16)b;
+    return r;
+  }
+  static __device__ __forceinline__ V raw(const s16* p) { return *reinterpret_cast<const V*>(p); }
+  static __device__ __forceinline__ float dot(V a, V b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+};
+template <>
+struct link16<sbf> {
+  using V = b2v;
+  static __device__ __forceinline__ V pk(float a, float b) {
+    V r;
+    r.x = (__bf16)a;
+    r.y = (__bf16)b;
+    return r;
+  }
+  static __device__ __forceinline__ V raw(const sbf* p) { return *reinterpret_cast<const V*>(p); }
+  static __device__ __forceinline__ float dot(V a, V b, float c) {
+    return __builtin_amdgcn_fdot2_f32_bf16(a, b, c, false);
+  }
+};
+
+template <typename SG>
+constexpr bool is_link16 = std::is_same<SG, s16>::value || std::is_same<SG, sbf>::value;
+
+// acc += (1 -/+ g_mu) W psi with 16-bit links; u(e) returns the raw packed entry e.
+template <int MU, int DIR, typename SG, typename PsiF, typename UF>
+__device__ __forceinline__ void hop16(cplx<float> acc[12], PsiF&& psi, UF&& u) {
+  using L = link16<SG>;
+  using V = typename L::V;
+  cplx<float> h0[3], h1[3];
+  proj<MU, DIR, float>(psi, h0, h1);
+  V a0[3], b0[3], a1[3], b1[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if constexpr (DIR > 0) {
+      a0[b] = L::pk(h0[b].re, -h0[b].im);
+      b0[b] = L::pk(h0[b].im, h0[b].re);
+      a1[b] = L::pk(h1[b].re, -h1[b].im);
+      b1[b] = L::pk(h1[b].im, h1[b].re);
+    } else {
+      a0[b] = L::pk(h0[b].re, h0[b].im);
+      b0[b] = L::pk(h0[b].im, -h0[b].re);
+      a1[b] = L::pk(h1[b].re, h1[b].im);
+      b1[b] = L::pk(h1[b].im, -h1[b].re);
+    }
+  }
+  cplx<float> g0[3], g1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const V w = u(DIR > 0 ? a * 3 + b : b * 3 + a);
+      r0 = L::dot(w, a0[b], r0);
+      i0 = L::dot(w, b0[b], i0);
+      r1 = L::dot(w, a1[b], r1);
+      i1 = L::dot(w, b1[b], i1);
+    }
+    g0[a] = mk(r0, i0);
+    g1[a] = mk(r1, i1);
+  }
+  recon_acc<MU, DIR, float>(acc, g0, g1);
+}
+
+template <typename SG, typename PsiF, typename UF>
+__device__ __forceinline__ void hop16_dispatch(int h, cplx<float> acc[12], PsiF&& psi, UF&& u) {
+  switch (h) {
+    case 0: hop16<0, +1, SG>(acc, psi, u); break;
+    case 1: hop16<0, -1, SG>(acc, psi, u); break;
+    case 2: hop16<1, +1, SG>(acc, psi, u); break;
+    case 3: hop16<1, -1, SG>(acc, psi, u); break;
+    case 4: hop16<2, +1, SG>(acc, psi, u); break;
+    case 5: hop16<2, -1, SG>(acc, psi, u); break;
+    case 6: hop16<3, +1, SG>(acc, psi, u); break;
+    default: hop16<3, -1, SG>(acc, psi, u); break;
+  }
+}
+
 // Hopping sum over all 8 neighbours on the periodic lattice, reading the
 // spinor through xin(block, local, comp) and links from U (internal layout).
 // The hop loop is deliberately not unrolled: unrolling lets the compiler
@@ -208,38 +305,51 @@ __device__ __forceinline__ void hop_sum_block(const Geom& g, int b, int l, const
 // u_blk(mu, e, local site); with HALO, neighbours in other blocks through
 // xin_halo(nb, nl, comp) and their links through u_halo(nb, mu, e, nl)
 // (hops leaving the block are dropped without HALO, eq. 2).
-template <typename T, bool HALO, typename XB, typename UB, typename XH, typename UH>
+// With LINK16 the link functors return raw packed 16-bit entries and the
+// hops use the dot-product form above (T must be float).
+// BS > 0 (a power of two): the block is BS^4, known at compile time, and
+// local coordinates are bit fields of the local index.
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+template <typename T, bool HALO, typename SG = void, int BS = 0, typename XB, typename UB, typename XH, typename UH>
 __device__ __forceinline__ void hop_sum_staged(const Geom& g, int b, int l, const int bc[4], const int lc[4],
                                                XB&& xin_blk, UB&& u_blk, XH&& xin_halo, UH&& u_halo,
                                                cplx<T> acc[12]) {
+  static_assert(BS == 0 || (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
+  constexpr int LB = ilog2(BS);
+  auto dispatch = [&](int h, auto&& psi, auto&& u) {
+    if constexpr (is_link16<SG>) hop16_dispatch<SG>(h, acc, psi, u);
+    else hop_dispatch<T>(h, acc, psi, u);
+  };
 #pragma unroll
   for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
 #pragma unroll 1
   for (int h = 0; h < 8; ++h) {
     const int mu = h >> 1;
     const bool fwd = (h & 1) == 0;
-    const int st = g.lstride[mu];
-    const bool inb = fwd ? lc[mu] < g.B[mu] - 1 : lc[mu] > 0;
+    const int st = BS > 0 ? 1 << (LB * mu) : g.lstride[mu];
+    const int bm = BS > 0 ? BS : g.B[mu];
+    const int lcm = BS > 0 ? (l >> (LB * mu)) & (BS - 1) : lc[mu];
+    const bool inb = fwd ? lcm < bm - 1 : lcm > 0;
     if (inb) {
       const int nl = fwd ? l + st : l - st;
       const int ul = fwd ? l : nl;
-      hop_dispatch<T>(h, acc, [&](int k) { return xin_blk(nl, k); }, [&](int e) { return u_blk(mu, e, ul); });
+      dispatch(h, [&](int k) { return xin_blk(nl, k); }, [&](int e) { return u_blk(mu, e, ul); });
     } else if constexpr (HALO) {
       int c2[4] = {bc[0], bc[1], bc[2], bc[3]};
       int nl;
       if (fwd) {
         c2[mu] = (bc[mu] + 1 == g.N[mu]) ? 0 : bc[mu] + 1;
-        nl = l - (g.B[mu] - 1) * st;
+        nl = l - (bm - 1) * st;
       } else {
         c2[mu] = (bc[mu] == 0) ? g.N[mu] - 1 : bc[mu] - 1;
-        nl = l + (g.B[mu] - 1) * st;
+        nl = l + (bm - 1) * st;
       }
       const int nb = encode_block(g, c2);
       if (fwd)
-        hop_dispatch<T>(h, acc, [&](int k) { return xin_halo(nb, nl, k); }, [&](int e) { return u_blk(mu, e, l); });
+        dispatch(h, [&](int k) { return xin_halo(nb, nl, k); }, [&](int e) { return u_blk(mu, e, l); });
       else
-        hop_dispatch<T>(h, acc, [&](int k) { return xin_halo(nb, nl, k); },
-                        [&](int e) { return u_halo(nb, mu, e, nl); });
+        dispatch(h, [&](int k) { return xin_halo(nb, nl, k); }, [&](int e) { return u_halo(nb, mu, e, nl); });
     }
   }
 }

@@ -33,17 +33,20 @@ __device__ __forceinline__ T wave_sum(T a) {
   return a;
 }
 
-template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL>
+// BS > 0: hypercubic BS^4 blocks known at compile time (LDS offsets and
+// link strides become immediates, local coordinates bit fields).
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS>
 __global__ void __launch_bounds__(MAXT)
     k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
                  int nmr, int z_zero, long long vs, long long zs, int nr, const int* __restrict__ rlist) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int bvol = BS > 0 ? BS * BS * BS * BS : g.bvol;
   // LDS: [links 36 x bvol (LDSL)] [rho 12 x bvol] [reduction 2 x nw x 3]
   SG* lks = reinterpret_cast<SG*>(smem);
-  const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
+  const size_t lbytes = LDSL ? (((size_t)36 * bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
   cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem + lbytes);
   const int nw = blockDim.x / kWave;
-  T* red = reinterpret_cast<T*>(rho_s + 12 * g.bvol);
+  T* red = reinterpret_cast<T*>(rho_s + 12 * bvol);
   // work item -> (block, right-hand side) with the RHS index fastest, so that
   // workgroups sharing a block's links run together on one XCD
   const int wi = xcd_remap(blockIdx.x, g.nbc * nr);
@@ -52,85 +55,90 @@ __global__ void __launch_bounds__(MAXT)
   const int rhs = rlist ? rlist[wi - jb * nr] : wi - jb * nr;
   const int b = colour_block(g, colour, jb);
   const int l = threadIdx.x;
-  const bool active = l < g.bvol;
+  const bool active = l < bvol;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const SV* vr = v + (long long)rhs * vs;
   SZ* zr = z + (long long)rhs * zs;
   const T half = (T)0.5;
 
+  // this block's spinors and links (contiguous chunks of the tiled layout)
+  const SV* vb = vr + (long long)b * 12 * bvol;
+  SZ* zb = zr + (long long)b * 12 * bvol;
+  const SG* Ub = U + (long long)b * 36 * bvol;
   int bc[4], lc[4] = {0, 0, 0, 0};
   decode_block(g, b, bc);
   if (active) decode_local(g, l, lc);
   // the block's links, read once per launch
   if constexpr (LDSL) {
     if (active)
-      for (int q = 0; q < 36; ++q) lks[q * g.bvol + l] = U[gauge_index(g, b, q / 9, q % 9, l)];
+      for (int q = 0; q < 36; ++q) lks[q * bvol + l] = Ub[q * bvol + l];
   }
-  auto u_blk = [&](int mu, int e, int ls) {
-    if constexpr (LDSL) return ld<T>(lks + (mu * 9 + e) * g.bvol + ls);
-    else return ld<T>(U + gauge_index(g, b, mu, e, ls));
+  // 16-bit links: hops take the raw packed entries (dot-product form)
+  constexpr bool L16 = is_link16<SG> && std::is_same<T, float>::value;
+  using LK = std::conditional_t<L16, SG, void>;
+  auto load_link = [&](const SG* p) {
+    if constexpr (L16) return link16<SG>::raw(p);
+    else return ld<T>(p);
   };
-  auto u_halo = [&](int nb, int mu, int e, int nl) { return ld<T>(U + gauge_index(g, nb, mu, e, nl)); };
+  auto u_blk = [&](int mu, int e, int ls) {
+    if constexpr (LDSL) return load_link(lks + (mu * 9 + e) * bvol + ls);
+    else return load_link(Ub + (mu * 9 + e) * bvol + ls);
+  };
+  auto u_halo = [&](int nb, int mu, int e, int nl) {
+    return load_link(U + ((long long)nb * 36 + mu * 9 + e) * bvol + nl);
+  };
 
-  cplx<T> rho[12], y[12];
+  // The MR residual rho lives in LDS only (neighbours read it there and
+  // each thread re-reads its own site), which keeps the register footprint
+  // low enough for four waves per SIMD.
+  cplx<T> y[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    rho[c] = mk<T>(0, 0);
-    y[c] = mk<T>(0, 0);
-  }
-  if (active) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) rho[c] = ld<T>(vr + spinor_index(g, b, c, l));
-  }
+  for (int c = 0; c < 12; ++c) y[c] = mk<T>(0, 0);
   if (!z_zero) {
     // block residual r = v - D z: z of this block staged in LDS, the one-site
     // halo of z read from the neighbouring blocks of the other colour
-    cplx<T> zo[12];
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        zo[c] = ld<T>(zr + spinor_index(g, b, c, l));
-        rho_s[c * g.bvol + l] = zo[c];
-      }
+      for (int c = 0; c < 12; ++c) rho_s[c * bvol + l] = ld<T>(zb + c * bvol + l);
     }
     __syncthreads();
+    cplx<T> acc[12];
     if (active) {
-      cplx<T> acc[12];
-      hop_sum_staged<T, true>(
-          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * g.bvol + nl]; }, u_blk,
-          [&](int nb, int nl, int k) { return ld<T>(zr + spinor_index(g, nb, k, nl)); }, u_halo, acc);
+      hop_sum_staged<T, true, LK, BS>(
+          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
+          [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); }, u_halo, acc);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) rho[c] = rho[c] - diag * zo[c] + half * acc[c];
+      for (int c = 0; c < 12; ++c)
+        acc[c] = ld<T>(vb + c * bvol + l) - diag * rho_s[c * bvol + l] + half * acc[c];
     }
     __syncthreads();  // z reads from LDS done before rho overwrites it
-  } else if constexpr (LDSL) {
-    __syncthreads();  // staged links visible
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) rho_s[c * bvol + l] = acc[c];
+    }
+  } else if (active) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho_s[c * bvol + l] = ld<T>(vb + c * bvol + l);
   }
 
   for (int it = 0; it < nmr; ++it) {
-    if (active) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) rho_s[c * g.bvol + l] = rho[c];
-    }
-    __syncthreads();
+    __syncthreads();  // rho (and staged links) visible to the whole block
     cplx<T> p[12];
     T nre = 0, nim = 0, den = 0;
     if (active) {
-      hop_sum_staged<T, false>(
-          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * g.bvol + nl]; }, u_blk,
+      hop_sum_staged<T, false, LK, BS>(
+          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
           [&](int, int, int) { return mk<T>(0, 0); }, u_halo, p);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        p[c] = diag * rho[c] - half * p[c];
-        cplx<T> d = cdot(p[c], rho[c]);
+        const cplx<T> r = rho_s[c * bvol + l];
+        p[c] = diag * r - half * p[c];
+        cplx<T> d = cdot(p[c], r);
         nre += d.re;
         nim += d.im;
         den += norm2(p[c]);
       }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) p[c] = mk<T>(0, 0);
     }
     nre = wave_sum(nre);
     nim = wave_sum(nim);
@@ -141,37 +149,40 @@ __global__ void __launch_bounds__(MAXT)
       rb[wave * 3 + 1] = nim;
       rb[wave * 3 + 2] = den;
     }
-    __syncthreads();
+    __syncthreads();  // also: every hop sum of this step has read rho
     nre = nim = den = 0;
     for (int w = 0; w < nw; ++w) {
       nre += rb[w * 3 + 0];
       nim += rb[w * 3 + 1];
       den += rb[w * 3 + 2];
     }
-    cplx<T> alpha = den > (T)0 ? mk<T>(nre / den, nim / den) : mk<T>(0, 0);
+    const cplx<T> alpha = den > (T)0 ? mk<T>(nre / den, nim / den) : mk<T>(0, 0);
+    if (active) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      y[c] += alpha * rho[c];
-      rho[c] -= alpha * p[c];
+      for (int c = 0; c < 12; ++c) {
+        const cplx<T> r = rho_s[c * bvol + l];
+        y[c] += alpha * r;
+        rho_s[c * bvol + l] = r - alpha * p[c];
+      }
     }
   }
   if (active) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const long long idx = spinor_index(g, b, c, l);
-      st(zr + idx, z_zero ? y[c] : ld<T>(zr + idx) + y[c]);
+      SZ* zp = zb + c * bvol + l;
+      st(zp, z_zero ? y[c] : ld<T>(zp) + y[c]);
     }
     // z starts at zero: this workgroup also clears one block of the other
     // colour (same count per colour), which this launch never reads
     if (z_zero) {
       const int bo = colour_block(g, 1 - colour, jb);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) st(zr + spinor_index(g, bo, c, l), mk<T>(0, 0));
+      for (int c = 0; c < 12; ++c) st(zr + ((long long)bo * 12 + c) * bvol + l, mk<T>(0, 0));
     }
   }
 }
 
-template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL>
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS = 0>
 dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
                    int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
   const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
@@ -183,7 +194,7 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
     return DW_EINVAL;
   }
   if (shmem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT, LDSL>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) {
       set_error("hipFuncSetAttribute(LDS %zu bytes) failed: %s", shmem, hipGetErrorString(e));
@@ -192,7 +203,7 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
   }
   dim3 grid((unsigned)xcd_grid(g.nbc * nrhs), 1);
   KTimer kt(DW_K_SAP, s);
-  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
+  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
                      (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs, nrhs, rlist);
   DW_CHECK_LAUNCH();
   // algorithmic traffic per site of this colour: v, 4 links, z read (or the
@@ -215,6 +226,10 @@ dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void*
   // than they gain from fewer cached link reads (measured on 4^4 blocks
   // with FP16 links: 380 us with links from L1/L2, 517 us staged).
   const size_t need = (size_t)36 * g.bvol * sizeof(SG) + (size_t)12 * g.bvol * sizeof(cplx<T>) + 512;
+  const bool hyper4 = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4;
+  if constexpr (MAXT == 256)
+    if (hyper4 && need > 40 * 1024)
+      return launch_t<T, SV, SZ, SG, 256, false, 4>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
   if (need <= 40 * 1024)
     return launch_t<T, SV, SZ, SG, MAXT, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
   return launch_t<T, SV, SZ, SG, MAXT, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);

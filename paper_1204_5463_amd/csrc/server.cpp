@@ -79,16 +79,31 @@ void worker(dw_server s) {
     std::shared_ptr<Req> rq;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      // FIFO admission: the head runs once its footprint fits beside the
-      // running requests. It always fits once none run (submit checked it
-      // against the whole budget), so the queue drains even after stop.
-      s->cv.wait(lk, [&] {
-        if (!s->queue.empty()) return s->in_use + (double)s->queue.front()->footprint <= s->budget;
-        return s->stop;
-      });
+      // Admission in arrival order with backfilling: the head runs once its
+      // footprint fits beside the running requests; a later request may
+      // run before it only if the memory the head needs stays free, so
+      // backfilled requests never delay the head's admission for memory.
+      // The head always fits once none run (submit checked it against the
+      // whole budget), so the queue drains, also after stop.
+      size_t pick = 0;
+      auto admissible = [&]() {
+        if (s->queue.empty()) return false;
+        const double head = (double)s->queue.front()->footprint;
+        if (s->in_use + head <= s->budget) {
+          pick = 0;
+          return true;
+        }
+        for (size_t i = 1; i < s->queue.size(); ++i)
+          if (s->in_use + head + (double)s->queue[i]->footprint <= s->budget) {
+            pick = i;
+            return true;
+          }
+        return false;
+      };
+      s->cv.wait(lk, [&] { return admissible() || (s->stop && s->queue.empty()); });
       if (s->queue.empty()) break;
-      rq = s->queue.front();
-      s->queue.pop_front();
+      rq = s->queue[pick];
+      s->queue.erase(s->queue.begin() + (long)pick);
       s->in_use += (double)rq->footprint;
       rq->state = DW_REQ_RUNNING;
       rq->t_start = now_s();
