@@ -333,6 +333,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--skip-dslash", action="store_true", help="skip the per-precision operator timings")
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
+    ap.add_argument("--params", default=None,
+                    help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4 (exploration)")
     ap.add_argument("--also-k0", action="store_true", help="also run FGMRES(m) (k = 0) on the same system")
     ap.add_argument("--sequential", action="store_true",
                     help="multi-RHS workloads: also time the RHS one after another")
@@ -342,7 +344,7 @@ def main():
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
     ap.add_argument("--max-rhs", type=int, default=4)
-    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -378,12 +380,26 @@ def main():
     del U
     bt = P.to_device(b)
     params = solver_params(P, wl, prec)
+    if args.params:
+        for kv in args.params.split(","):
+            key, val = kv.split("=")
+            if key == "s":
+                params.sap.ncycles = int(val)
+            elif key == "nmr":
+                params.sap.nmr = int(val)
+            elif key == "block":
+                params.sap.block = tuple(int(t) for t in val.split("x"))
+            elif key in ("m", "k"):
+                setattr(params, key, int(val))
+            else:
+                raise SystemExit(f"unknown parameter {key}")
     tune = None
     if args.autotune:
         log("[bench] autotuning (untimed)")
         ts = time.perf_counter()
-        space = P.TuneSpace(nmr=(3, 7), s=(1, 3), mk=((wl["m"], wl["k"] // 2), (wl["m"] - 6, wl["k"] - 4)),
-                            iter_cap=2.0)
+        space = P.TuneSpace(nmr=(4, 10), s=(2, 5),
+                            mk=((30, 6), (30, 10), (24, 6), (24, 10), (20, 6), (36, 8), (40, 10), (48, 12)),
+                            passes=2, iter_cap=2.0)
         params, trials = P.autotune(ctx, L, Ud, m0, params, bt, space=space, cache=P.TuneCache(args.autotune))
         for t in trials:
             log(f"[bench]   trial {t}")
@@ -419,6 +435,14 @@ def main():
     value = nrhs * args.steps / elapsed
     stl = stats[-1]
     st0 = max(stl, key=lambda s: s.iterations)
+
+    # the same solve without per-launch event timing (wall clock only)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    f.solve(m0, params, bt)
+    torch.cuda.synchronize()
+    unprofiled_ms = 1000 * (time.perf_counter() - ts)
+    log(f"[bench] solve without event timing: {unprofiled_ms:.1f} ms")
 
     # independent FP64 residual check of the last solutions (library FP64 operator)
     relres_check = 0.0
@@ -552,6 +576,7 @@ def main():
         "clean_restarts": st0.clean_restarts,
         "true_relres": st0.true_relres,
         "true_relres_check": relres_check,
+        "ms_per_step_without_event_timing": round(unprofiled_ms, 2),
         "p50_ms": round(lat_ms[len(lat_ms) // 2], 2),
         "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)], 2),
         "roofline": roofline,

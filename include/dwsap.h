@@ -182,7 +182,8 @@ dw_status fgmresdr_solve(dw_field field, double m0, const fgmresdr_params* param
  * A server solves requests of different lattices, masses and RHS counts
  * with continuous batching: requests are queued in arrival order and
  * admitted when a slot is free and their device-memory footprint fits the
- * budget beside the requests already running; each slot runs its request
+ * budget beside the requests already running (a later request may go first
+ * only if it leaves room for the oldest waiting one); each slot runs its request
  * on its own HIP stream, so admitted requests overlap on the device, and
  * keeps the request's gauge copies and Krylov / deflation state on the
  * device until the request completes. Server memory is stream-ordered
@@ -242,7 +243,7 @@ dw_status solve_poll(dw_server server, uint64_t ticket, dw_req_state* state, dw_
  * iteration, the tuner's objective is the wall-clock time of the whole
  * solve to the requested tolerance. It searches coordinate-wise from
  * `base`: block shape, then nmr, then s, then (m, k), keeping the best so
- * far each time; a candidate's max_iter is capped at `iter_cap` times the
+ * far each time and repeating the last three `passes` times; a candidate's max_iter is capped at `iter_cap` times the
  * best iteration count so far, so hopeless candidates stop early. */
 typedef struct dw_tune_space {
   int32_t nblocks;        /* candidate block shapes in blocks[]; 0 = every shape with extents in
@@ -253,6 +254,7 @@ typedef struct dw_tune_space {
   int32_t nmk;               /* (m, k) candidates in mk[] (0: keep base) */
   int32_t mk[8][2];
   int32_t repeats;           /* timed solves per candidate, the fastest counts (>= 1) */
+  int32_t passes;            /* sweeps over (nmr, s, (m, k)) after the block search (>= 1) */
   double iter_cap;           /* max_iter of a candidate = iter_cap * best iterations (<= 0: base max_iter) */
 } dw_tune_space;
 

@@ -94,7 +94,7 @@ class _TuneSpace(ctypes.Structure):
                 ("nmr_min", ctypes.c_int32), ("nmr_max", ctypes.c_int32),
                 ("s_min", ctypes.c_int32), ("s_max", ctypes.c_int32),
                 ("nmk", ctypes.c_int32), ("mk", (ctypes.c_int32 * 2) * 8),
-                ("repeats", ctypes.c_int32), ("iter_cap", ctypes.c_double)]
+                ("repeats", ctypes.c_int32), ("passes", ctypes.c_int32), ("iter_cap", ctypes.c_double)]
 
 
 class _TuneTrial(ctypes.Structure):
@@ -475,6 +475,7 @@ class TuneSpace:
     s: tuple = (1, 4)
     mk: tuple = ()
     repeats: int = 1
+    passes: int = 1
     iter_cap: float = 3.0
 
     def _c(self):
@@ -490,7 +491,7 @@ class TuneSpace:
         t.nmk = len(self.mk)
         for i, (m, k) in enumerate(self.mk):
             t.mk[i][0], t.mk[i][1] = int(m), int(k)
-        t.repeats, t.iter_cap = int(self.repeats), float(self.iter_cap)
+        t.repeats, t.passes, t.iter_cap = int(self.repeats), int(self.passes), float(self.iter_cap)
         return t
 
 

@@ -20,6 +20,8 @@ constexpr int kThreads = 256;
 constexpr int kWave = 64;
 constexpr int kDotCols = 8;   // columns per multi-dot pass
 constexpr int kRotMax = 24;   // output columns of one rotation pass
+constexpr int kGsCols = 8;    // columns per pass of the Gram-Schmidt reduction
+constexpr int kUpd = 8;       // columns loaded together by the Gram-Schmidt update
 
 __device__ __forceinline__ double wsum(double a) {
 #pragma unroll
@@ -168,7 +170,7 @@ template <bool HU, bool HW>
 __global__ void __launch_bounds__(kThreads)
     k_gs_reduce(const s64* __restrict__ V, long long stride, int c0, int nc, int nv, const s64* __restrict__ u,
                 const s64* __restrict__ w, long long n, int first, s64* __restrict__ partials) {
-  constexpr int NA = kDotCols;
+  constexpr int NA = kGsCols;
   __shared__ double red[kThreads / kWave][2 * NA + 3][2];
   cplx<double> au[NA], aw[NA], uu = mk(0.0, 0.0), uw = mk(0.0, 0.0), ww = mk(0.0, 0.0);
 #pragma unroll
@@ -255,7 +257,20 @@ __global__ void __launch_bounds__(kThreads)
     cplx<double> uu = mk(0.0, 0.0), wa = mk(0.0, 0.0);
     if constexpr (HU) uu = ld<double>(V + (long long)jcol * stride + i);
     if constexpr (HW) wa = ld<double>(w + i);
-    for (int c = 0; c < nv; ++c) {
+    // columns in groups of kUpd with all loads of a group issued together,
+    // so that each thread keeps several HBM reads in flight
+    int c = 0;
+    for (; c + kUpd <= nv; c += kUpd) {
+      cplx<double> vc[kUpd];
+#pragma unroll
+      for (int q = 0; q < kUpd; ++q) vc[q] = ld<double>(V + (long long)(c + q) * stride + i);
+#pragma unroll
+      for (int q = 0; q < kUpd; ++q) {
+        if constexpr (HU) uu -= ca[c + q] * vc[q];
+        if constexpr (HW) wa -= cb[c + q] * vc[q];
+      }
+    }
+    for (; c < nv; ++c) {
       const cplx<double> vc = ld<double>(V + (long long)c * stride + i);
       if constexpr (HU) uu -= ca[c] * vc;
       if constexpr (HW) wa -= cb[c] * vc;
@@ -377,10 +392,13 @@ dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, 
     return DW_EINVAL;
   }
   const unsigned G = grid_for(n);
-  const int nchunks = nv > 0 ? (nv + kDotCols - 1) / kDotCols : 1;
+  // the columns in as few passes as possible, split evenly (u and w are
+  // re-read by every pass)
+  const int nchunks = nv > 0 ? (nv + kGsCols - 1) / kGsCols : 1;
+  const int per = nv > 0 ? (nv + nchunks - 1) / nchunks : 0;
   for (int q = 0; q < nchunks; ++q) {
-    const int c0 = q * kDotCols;
-    const int nc = nv - c0 < kDotCols ? nv - c0 : kDotCols;
+    const int c0 = q * per;
+    const int nc = nv - c0 < per ? nv - c0 : per;
     KTimer kt(DW_K_DOTS, s);
     const s64* Vp = (const s64*)V;
     const s64 *up = (const s64*)u, *wp = (const s64*)w;

@@ -175,22 +175,24 @@ extern "C" dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U
     std::copy(B.begin(), B.end(), p.sap.block);
     step(p);
   }
-  // MR steps, SAP cycles, (m, k)
-  for (int nmr = space->nmr_min; nmr <= space->nmr_max && nmr >= 0; ++nmr) {
-    fgmresdr_params p = T.current(*base);
-    p.sap.nmr = nmr;
-    step(p);
-  }
-  for (int c = space->s_min; c <= space->s_max && c >= 1; ++c) {
-    fgmresdr_params p = T.current(*base);
-    p.sap.ncycles = c;
-    step(p);
-  }
-  for (int i = 0; i < space->nmk; ++i) {
-    fgmresdr_params p = T.current(*base);
-    p.m = space->mk[i][0];
-    p.k = space->mk[i][1];
-    step(p);
+  // MR steps, SAP cycles, (m, k); they interact, so the sweep is repeated
+  for (int pass = 0; pass < std::max(1, space->passes); ++pass) {
+    for (int nmr = space->nmr_min; nmr <= space->nmr_max && nmr >= 0; ++nmr) {
+      fgmresdr_params p = T.current(*base);
+      p.sap.nmr = nmr;
+      step(p);
+    }
+    for (int c = space->s_min; c <= space->s_max && c >= 1; ++c) {
+      fgmresdr_params p = T.current(*base);
+      p.sap.ncycles = c;
+      step(p);
+    }
+    for (int i = 0; i < space->nmk; ++i) {
+      fgmresdr_params p = T.current(*base);
+      p.m = space->mk[i][0];
+      p.k = space->mk[i][1];
+      step(p);
+    }
   }
   *ntrials = T.n;
   if (s != DW_OK) return s;
