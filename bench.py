@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--skip-dslash", action="store_true", help="skip the per-precision operator timings")
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
     ap.add_argument("--params", default=None,
-                    help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4 (exploration)")
+                    help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4,shared=1 (exploration)")
     ap.add_argument("--also-k0", action="store_true", help="also run FGMRES(m) (k = 0) on the same system")
     ap.add_argument("--sequential", action="store_true",
                     help="multi-RHS workloads: also time the RHS one after another")
@@ -391,6 +391,8 @@ def main():
                 params.sap.block = tuple(int(t) for t in val.split("x"))
             elif key in ("m", "k"):
                 setattr(params, key, int(val))
+            elif key == "shared":
+                params.shared_defl = int(val)
             else:
                 raise SystemExit(f"unknown parameter {key}")
     tune = None

@@ -95,8 +95,13 @@ typedef struct sap_params {
  *   restart_t  clean restart (no deflation) when ||r_explicit|| / ||r_implicit||
  *              exceeds this threshold (the paper suggests 2..10).
  *   sap        preconditioner parameters.
- *   shared_defl  must be 0 (a shared multi-RHS deflation space is not
- *              provided; every RHS deflates with its own harmonic Ritz vectors).
+ *   shared_defl  multi-RHS only: 1 = once the batch's first RHS has a
+ *              deflation space (D Z_k = V_{k+1} H_k from its last deflated
+ *              restart), every other RHS of the lock-step batch projects its
+ *              residual onto that space at each restart (minimum residual
+ *              over span Z_k) and restarts with a fresh Krylov space, as in
+ *              GMRES with projection; 0 = independent FGMRES-DR solves. Not
+ *              in the paper; the projection cannot raise the residual.
  *   flags      reserved, pass 0. */
 typedef struct fgmresdr_params {
   int32_t m;

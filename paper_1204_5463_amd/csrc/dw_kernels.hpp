@@ -77,6 +77,9 @@ dw_status dense_gs_coef(double* H, int nv, int jcol, int jw, int hu, int hw, con
 // scal[kSclHinv] = 1/H(j+1, j) for scaling the next preconditioner input.
 dw_status dense_step2(double* H, int j, const double* nrm2, const double* c, double* scal, double bd_tol,
                       hipStream_t s);
+// projection onto a deflation space with D Z_k = V_{k+1} H_k (H_k the
+// (k+1) x k leading block of H): y = argmin ||t - H_k y||, sv = H_k y
+dw_status dense_project(const double* H, int k, const double* t, double* y, double* sv, hipStream_t s);
 // fresh start: scal[kSclBeta] = sqrt(nrm2.re), scal[kSclBetaInv] = 1/beta, c = beta e_1, H = 0
 dw_status dense_fresh(double* H, double* c, const double* nrm2, double* scal, hipStream_t s);
 

@@ -106,6 +106,33 @@ struct storage_traits<sbf> {
 
 template <typename T, typename S>
 __device__ __forceinline__ cplx<T> ld(const S* p) { return storage_traits<S>::template load<T>(*p); }
+
+// Streaming (non-temporal) load and store of one complex pair: for data read
+// or written once per kernel, so that it does not evict reused data from
+// the caches. The pair moves as one vector of its own size.
+template <int BYTES> struct nt_vec;
+template <> struct nt_vec<16> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct nt_vec<8> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct nt_vec<4> { typedef uint32_t type; };
+
+template <typename S>
+__device__ __forceinline__ S ld_nt_raw(const S* p) {
+  using V = typename nt_vec<sizeof(S)>::type;
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  S s;
+  __builtin_memcpy(&s, &v, sizeof(S));
+  return s;
+}
+template <typename T, typename S>
+__device__ __forceinline__ cplx<T> ld_nt(const S* p) { return storage_traits<S>::template load<T>(ld_nt_raw(p)); }
+template <typename T, typename S>
+__device__ __forceinline__ void st_nt(S* p, cplx<T> c) {
+  using V = typename nt_vec<sizeof(S)>::type;
+  const S s = storage_traits<S>::template store<T>(c);
+  V v;
+  __builtin_memcpy(&v, &s, sizeof(S));
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
 template <typename T, typename S>
 __device__ __forceinline__ void st(S* p, cplx<T> c) { *p = storage_traits<S>::template store<T>(c); }
 

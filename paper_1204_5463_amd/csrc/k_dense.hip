@@ -237,6 +237,35 @@ __global__ void __launch_bounds__(kL) k_lsq(const double* H, int cols, const dou
   if (lane == 0) scal[kSclResImp] = cabs(S.rhs[rows - 1]);
 }
 
+// Projection onto a deflation space (D Z_k = V_{k+1} H_k): y = argmin ||t - H_k y||
+// and s = H_k y, with H_k the (k+1) x k leading block of H.
+__global__ void __launch_bounds__(kL) k_project(const double* H, int k, const double* t, double* y, double* sv) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  StepSmem& S = *reinterpret_cast<StepSmem*>(smem_raw);
+  const int lane = threadIdx.x;
+  const int rows = k + 1;
+  for (int q = lane; q < rows * k; q += kL) {
+    const int i = q % rows, c = q / rows;
+    S.A[i + c * kLd] = ldc(H, i + (long long)c * kLd);
+  }
+  if (lane < rows) S.rhs[lane] = ldc(t, lane);
+  __syncthreads();
+  hh_qr(S.A, kLd, rows, k, S.rhs, S.Uv, kLd, S.beta);
+  back_subst(S.A, kLd, k, S.rhs, S.eta);
+  __syncthreads();
+  if (lane < k) stc(y, lane, S.eta[lane]);
+  if (lane < rows) {
+    C acc{0, 0};
+    for (int c = 0; c < k; ++c) {
+      const C h = ldc(H, lane + (long long)c * kLd);
+      const C e = S.eta[c];
+      acc.re += h.re * e.re - h.im * e.im;
+      acc.im += h.re * e.im + h.im * e.re;
+    }
+    stc(sv, lane, acc);
+  }
+}
+
 __global__ void __launch_bounds__(kL) k_fresh(double* H, double* c, const double* nrm2, double* scal) {
   const int lane = threadIdx.x;
   const double beta = sqrt(fmax(nrm2[0], 0.0));
@@ -622,6 +651,19 @@ dw_status dense_lsq(const double* H, int cols, const double* c, double* eta, dou
   DW_TRY(set_lds(k_lsq, sizeof(StepSmem)));
   KTimer kt(DW_K_DENSE, s);
   hipLaunchKernelGGL(k_lsq, 1, kL, sizeof(StepSmem), s, H, cols, c, eta, scal);
+  DW_CHECK_LAUNCH();
+  kt.done(0, 0);
+  return DW_OK;
+}
+
+dw_status dense_project(const double* H, int k, const double* t, double* y, double* sv, hipStream_t s) {
+  if (k < 1 || k >= kMaxM) {
+    set_error("dense_project: k = %d out of range", k);
+    return DW_EINVAL;
+  }
+  DW_TRY(set_lds(k_project, sizeof(StepSmem)));
+  KTimer kt(DW_K_DENSE, s);
+  hipLaunchKernelGGL(k_project, 1, kL, sizeof(StepSmem), s, H, k, t, y, sv);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;

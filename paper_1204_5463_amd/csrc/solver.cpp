@@ -52,7 +52,7 @@ namespace {
 struct Work {
   int nr = 0, m = 0;
   long long n = 0;
-  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal, rlist;
+  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal, rlist, proj;
   double* scal_h = nullptr;  // nr x (kSclCount + 2): scalars and the pair nrm
   int* rlist_h = nullptr;
   ~Work() {
@@ -73,6 +73,8 @@ struct Work {
   double* scalr(int r) const { return scal.as<double>() + (long long)r * kSclCount; }
   double* partr(int r) const { return partials.as<double>() + 2 * (long long)r * (2 * kLd + 6) * kBlasGrid; }
   const double* sh(int r) const { return scal_h + (long long)r * (kSclCount + 2); }
+  // shared-deflation projection: t = V_0^H r (kLd pairs), y (kMaxM), s = H_0 y (kLd)
+  double* projr(int r) const { return proj.as<double>() + 2 * (long long)r * (2 * kLd + kMaxM); }
 };
 
 size_t bytes_per_rhs(long long n, int m, int prec) {
@@ -107,6 +109,7 @@ dw_status alloc_work(dw_field f, const fgmresdr_params* P, int nr, Work& W, hipS
   DW_TRY(W.Q.alloc(ctx, (size_t)nr * kLd * 25 * 16, s));
   DW_TRY(W.ritz.alloc(ctx, (size_t)nr * kMaxM * 16, s));
   DW_TRY(W.scal.alloc(ctx, (size_t)nr * kSclCount * 8, s));
+  if (P->shared_defl && nr > 1) DW_TRY(W.proj.alloc(ctx, (size_t)nr * (2 * kLd + kMaxM) * 16, s));
   DW_TRY(W.rlist.alloc(ctx, (size_t)nr * sizeof(int), s));
   DW_CHECK_HIP(hipHostMalloc((void**)&W.scal_h, (size_t)nr * (kSclCount + 2) * sizeof(double), hipHostMallocDefault));
   DW_CHECK_HIP(hipHostMalloc((void**)&W.rlist_h, (size_t)nr * sizeof(int), hipHostMallocDefault));
@@ -156,6 +159,7 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
   const double bd_tol = 1e-14;
   auto t0 = std::chrono::steady_clock::now();
   std::vector<Rhs> R(nr);
+  bool donor_ok = false;  // RHS 0 holds a deflation space from a deflated restart
 
   DW_TRY(launch_pack_spinor(g, DW_PREC_F64, b_can, W.b.p, 1.0, nr, s));
   DW_CHECK_HIP(hipMemsetAsync(W.x.p, 0, (size_t)nr * n * 16, s));
@@ -264,6 +268,29 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
     DW_TRY(set_rlist(W, cyc, s));
     DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.x.p, 1.0, f->U[DW_PREC_F64], W.r.as<double>(), W.b.as<double>(),
                                1, (int)cyc.size(), n, n, s, W.rlist.as<int>()));
+    // shared deflation space (multi-RHS): once RHS 0 has a deflation space,
+    // every other RHS projects its restart residual onto it. The space
+    // satisfies D Z_0 = V_0 H_0 (the k+1 leading columns of V_0, k of Z_0 and
+    // the (k+1) x k block H_0 kept from RHS 0's last deflated restart), so
+    // y = argmin ||V_0^H r - H_0 y|| minimises ||r - D Z_0 y||; then
+    // x += Z_0 y, r -= V_0 H_0 y, and that RHS restarts from the projected
+    // residual with a fresh Krylov space (the projected residual is no
+    // longer in the span of its own deflation basis).
+    std::vector<char> projected(nr, 0);
+    if (P->shared_defl && nr > 1 && k > 0 && donor_ok) {
+      for (int r : cyc) {
+        if (r == 0) continue;
+        projected[r] = 1;
+        double* pr = W.projr(r);
+        double* t = pr;
+        double* y = pr + 2 * kLd;
+        double* sv = y + 2 * kMaxM;
+        DW_TRY(blas_dots(DW_PREC_F64, W.Vr(0), n, k + 1, W.vec(W.r, r), n, W.partr(r), t, 1, 0, s));
+        DW_TRY(dense_project(W.Hr(0), k, t, y, sv, s));
+        DW_TRY(blas_combine(DW_PREC_F64, W.Zr(0), n, k, y, 1.0, W.vec(W.x, r), n, s));
+        DW_TRY(blas_combine(DW_PREC_F64, W.Vr(0), n, k + 1, sv, -1.0, W.vec(W.r, r), n, s));
+      }
+    }
     for (int r : cyc)
       DW_TRY(blas_dots(DW_PREC_F64, W.vec(W.r, r), n, 1, W.vec(W.r, r), n, W.partr(r), W.nrmr(r), 1, 0, s));
     DW_TRY(readback(W, s));
@@ -278,10 +305,11 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         q.done = q.converged = true;
       } else if (q.iters >= P->max_iter) {
         q.done = true;
-      } else if (k == 0) {
-        // plain restarted FGMRES(m)
+      } else if (k == 0 || projected[r]) {
+        // plain restarted FGMRES(m), or a restart from a projected residual
       } else if (q.broke || q.jend <= k || q.res_e > P->restart_t * fmax(q.res_i, 1e-300)) {
         ++q.clean;  // clean restart (Section 4.7)
+        if (r == 0) donor_ok = false;
       } else {
         defl.push_back(r);
       }
@@ -294,8 +322,10 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         Rhs& q = R[r];
         if (W.sh(r)[kSclStatus] != 0.0) {
           ++q.clean;
+          if (r == 0) donor_ok = false;
           continue;
         }
+        if (r == 0) donor_ok = true;
         DW_TRY(blas_rotate(DW_PREC_F64, W.Vr(r), n, q.jend + 1, W.Qr(r), kLd, k + 1, n, s));
         DW_TRY(blas_rotate(DW_PREC_F64, W.Zr(r), n, q.jend, W.Qr(r), kLd, k, n, s));
         DW_CHECK_HIP(hipMemsetAsync(W.cr(r), 0, (size_t)kLd * 16, s));
@@ -345,8 +375,8 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
     return DW_EINVAL;
   }
   DW_TRY(check_sap_params(f->g, &P->sap));
-  if (P->shared_defl != 0) {
-    set_error("fgmresdr_solve: shared_defl must be 0");
+  if (P->shared_defl != 0 && P->shared_defl != 1) {
+    set_error("fgmresdr_solve: shared_defl must be 0 or 1");
     return DW_EINVAL;
   }
   if (P->sap.ncycles < 1) {
