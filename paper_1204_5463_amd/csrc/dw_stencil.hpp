@@ -240,6 +240,76 @@ __device__ __forceinline__ void hop16(cplx<float> acc[12], PsiF&& psi, UF&& u) {
   recon_acc<MU, DIR, float>(acc, g0, g1);
 }
 
+// Fully packed FP16 variant: the neighbour spinor is already FP16 (packed
+// (re, im) pairs) and the projection is done in packed FP16 arithmetic,
+// producing the two dot-product operands of each half-spinor entry directly
+// (the lane swaps and sign flips fold into the packed adds' operand
+// modifiers). Accumulation stays FP32.
+template <int K>
+__device__ __forceinline__ h2v cmul16(h2v b) {
+  if constexpr (K == CP1) return b;
+  else if constexpr (K == CM1) return h2v{-b.x, -b.y};
+  else if constexpr (K == CPI) return h2v{-b.y, b.x};
+  else return h2v{b.y, -b.x};
+}
+__device__ __forceinline__ h2v cj16(h2v v) { return h2v{v.x, -v.y}; }
+__device__ __forceinline__ h2v sw16(h2v v) { return h2v{v.y, v.x}; }
+__device__ __forceinline__ h2v swn16(h2v v) { return h2v{v.y, -v.x}; }
+
+template <int MU, int DIR, typename PsiF, typename UF>
+__device__ __forceinline__ void hop16p(cplx<float> acc[12], PsiF&& psi, UF&& u) {
+  using P = proj_table<MU>;
+  constexpr int A = DIR > 0 ? P::a : neg(P::a);
+  constexpr int B = DIR > 0 ? P::b : neg(P::b);
+  h2v a0[3], b0[3], a1[3], b1[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const h2v p0 = psi(b), q0 = cmul16<A>(psi(P::pa * 3 + b));
+    const h2v p1 = psi(3 + b), q1 = cmul16<B>(psi(P::pb * 3 + b));
+    if constexpr (DIR > 0) {
+      a0[b] = cj16(p0) + cj16(q0);
+      b0[b] = sw16(p0) + sw16(q0);
+      a1[b] = cj16(p1) + cj16(q1);
+      b1[b] = sw16(p1) + sw16(q1);
+    } else {
+      a0[b] = p0 + q0;
+      b0[b] = swn16(p0) + swn16(q0);
+      a1[b] = p1 + q1;
+      b1[b] = swn16(p1) + swn16(q1);
+    }
+  }
+  cplx<float> g0[3], g1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const h2v w = u(DIR > 0 ? a * 3 + b : b * 3 + a);
+      r0 = __builtin_amdgcn_fdot2(w, a0[b], r0, false);
+      i0 = __builtin_amdgcn_fdot2(w, b0[b], i0, false);
+      r1 = __builtin_amdgcn_fdot2(w, a1[b], r1, false);
+      i1 = __builtin_amdgcn_fdot2(w, b1[b], i1, false);
+    }
+    g0[a] = mk(r0, i0);
+    g1[a] = mk(r1, i1);
+  }
+  recon_acc<MU, DIR, float>(acc, g0, g1);
+}
+
+template <typename PsiF, typename UF>
+__device__ __forceinline__ void hop16p_dispatch(int h, cplx<float> acc[12], PsiF&& psi, UF&& u) {
+  switch (h) {
+    case 0: hop16p<0, +1>(acc, psi, u); break;
+    case 1: hop16p<0, -1>(acc, psi, u); break;
+    case 2: hop16p<1, +1>(acc, psi, u); break;
+    case 3: hop16p<1, -1>(acc, psi, u); break;
+    case 4: hop16p<2, +1>(acc, psi, u); break;
+    case 5: hop16p<2, -1>(acc, psi, u); break;
+    case 6: hop16p<3, +1>(acc, psi, u); break;
+    default: hop16p<3, -1>(acc, psi, u); break;
+  }
+}
+
 template <typename SG, typename PsiF, typename UF>
 __device__ __forceinline__ void hop16_dispatch(int h, cplx<float> acc[12], PsiF&& psi, UF&& u) {
   switch (h) {
@@ -305,8 +375,10 @@ __device__ __forceinline__ void hop_sum_block(const Geom& g, int b, int l, const
 // u_blk(mu, e, local site); with HALO, neighbours in other blocks through
 // xin_halo(nb, nl, comp) and their links through u_halo(nb, mu, e, nl)
 // (hops leaving the block are dropped without HALO, eq. 2).
-// With LINK16 the link functors return raw packed 16-bit entries and the
-// hops use the dot-product form above (T must be float).
+// With SG = s16 / sbf the link functors return raw packed 16-bit entries
+// and the hops use the dot-product form above (T must be float); with
+// SG = h2v the block spinor functor also returns packed FP16 pairs and the
+// projection is packed too (in-block hops only).
 // BS > 0 (a power of two): the block is BS^4, known at compile time, and
 // local coordinates are bit fields of the local index.
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
@@ -318,7 +390,8 @@ __device__ __forceinline__ void hop_sum_staged(const Geom& g, int b, int l, cons
   static_assert(BS == 0 || (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
   constexpr int LB = ilog2(BS);
   auto dispatch = [&](int h, auto&& psi, auto&& u) {
-    if constexpr (is_link16<SG>) hop16_dispatch<SG>(h, acc, psi, u);
+    if constexpr (std::is_same<SG, h2v>::value) hop16p_dispatch(h, acc, psi, u);
+    else if constexpr (is_link16<SG>) hop16_dispatch<SG>(h, acc, psi, u);
     else hop_dispatch<T>(h, acc, psi, u);
   };
 #pragma unroll

@@ -17,6 +17,8 @@
 // race-free. Arithmetic is T (float for FP32/FP16/BF16 storage, double for
 // FP64 storage); the block inner products are wavefront reductions followed
 // by a fixed-order sum over the workgroup's waves (deterministic).
+#include <type_traits>
+
 #include "dw_internal.hpp"
 #include "dw_stencil.hpp"
 
@@ -26,11 +28,30 @@ namespace {
 
 constexpr int kWave = 64;
 
+// Wavefront sum. FP32: an inclusive scan within each row of 16 lanes by
+// DPP row shifts, then the row totals combined by the row broadcasts, so
+// that lane 63 holds the sum (no LDS traffic); its value is returned to all
+// lanes. FP64 goes through cross-lane shuffles.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false);
+  return v + __int_as_float(s);
+}
 template <typename T>
 __device__ __forceinline__ T wave_sum(T a) {
+  if constexpr (std::is_same<T, float>::value) {
+    a = dpp_add<0x111, 0xf>(a);  // row_shr:1
+    a = dpp_add<0x112, 0xf>(a);  // row_shr:2
+    a = dpp_add<0x114, 0xf>(a);  // row_shr:4
+    a = dpp_add<0x118, 0xf>(a);  // row_shr:8
+    a = dpp_add<0x142, 0xa>(a);  // row_bcast:15 into rows 1 and 3
+    a = dpp_add<0x143, 0xc>(a);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a), 63));
+  } else {
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
-  return a;
+    for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+    return a;
+  }
 }
 
 // BS > 0: hypercubic BS^4 blocks known at compile time (LDS offsets and
@@ -46,7 +67,14 @@ __global__ void __launch_bounds__(MAXT)
   const size_t lbytes = LDSL ? (((size_t)36 * bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
   cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem + lbytes);
   const int nw = blockDim.x / kWave;
-  T* red = reinterpret_cast<T*>(rho_s + 12 * bvol);
+  // FP16 storage: a packed FP16 copy of rho for the neighbours' hops
+  constexpr bool P16 = std::is_same<SG, s16>::value && std::is_same<T, float>::value;
+  h2v* rho16 = reinterpret_cast<h2v*>(rho_s + 12 * bvol);
+  T* red = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(rho_s + 12 * bvol) + (P16 ? 12 * bvol * 4 : 0));
+  auto put_rho = [&](int c, int site, cplx<T> r) {
+    rho_s[c * bvol + site] = r;
+    if constexpr (P16) rho16[c * bvol + site] = link16<s16>::pk(r.re, r.im);
+  };
   // work item -> (block, right-hand side) with the RHS index fastest, so that
   // workgroups sharing a block's links run together on one XCD
   const int wi = xcd_remap(blockIdx.x, g.nbc * nr);
@@ -115,11 +143,11 @@ __global__ void __launch_bounds__(MAXT)
     __syncthreads();  // z reads from LDS done before rho overwrites it
     if (active) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) rho_s[c * bvol + l] = acc[c];
+      for (int c = 0; c < 12; ++c) put_rho(c, l, acc[c]);
     }
   } else if (active) {
 #pragma unroll
-    for (int c = 0; c < 12; ++c) rho_s[c * bvol + l] = ld<T>(vb + c * bvol + l);
+    for (int c = 0; c < 12; ++c) put_rho(c, l, ld<T>(vb + c * bvol + l));
   }
 
   for (int it = 0; it < nmr; ++it) {
@@ -127,9 +155,14 @@ __global__ void __launch_bounds__(MAXT)
     cplx<T> p[12];
     T nre = 0, nim = 0, den = 0;
     if (active) {
-      hop_sum_staged<T, false, LK, BS>(
-          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
-          [&](int, int, int) { return mk<T>(0, 0); }, u_halo, p);
+      if constexpr (P16)
+        hop_sum_staged<T, false, h2v, BS>(
+            g, b, l, bc, lc, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,
+            [&](int, int, int) { return h2v{0, 0}; }, u_halo, p);
+      else
+        hop_sum_staged<T, false, LK, BS>(
+            g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
+            [&](int, int, int) { return mk<T>(0, 0); }, u_halo, p);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const cplx<T> r = rho_s[c * bvol + l];
@@ -162,7 +195,7 @@ __global__ void __launch_bounds__(MAXT)
       for (int c = 0; c < 12; ++c) {
         const cplx<T> r = rho_s[c * bvol + l];
         y[c] += alpha * r;
-        rho_s[c * bvol + l] = r - alpha * p[c];
+        put_rho(c, l, r - alpha * p[c]);
       }
     }
   }
@@ -187,8 +220,9 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
                    int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
   const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
   const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
-  const size_t shmem =
-      lbytes + (size_t)12 * g.bvol * sizeof(cplx<T>) + (size_t)2 * 3 * (threads / kWave) * sizeof(T);
+  constexpr bool P16 = std::is_same<SG, s16>::value && std::is_same<T, float>::value;
+  const size_t shmem = lbytes + (size_t)12 * g.bvol * sizeof(cplx<T>) + (P16 ? (size_t)12 * g.bvol * 4 : 0) +
+                       (size_t)2 * 3 * (threads / kWave) * sizeof(T);
   if (shmem > 160 * 1024) {
     set_error("SAP block of %d sites needs %zu bytes of LDS", g.bvol, shmem);
     return DW_EINVAL;
