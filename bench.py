@@ -242,8 +242,9 @@ def serve(args):
         r["b"] = P.to_device(synth.gaussian_spinors(SERVE_LATTICES[r["lattice"]], r["nrhs"], seed0=r["seed"]))
     log(f"[serve] {len(reqs)} requests over {t:.2f} s of arrivals")
 
-    def params(storage):
+    def params(storage, graphs=False):
         return P.SolverParams(m=30, k=12, tol=1e-10, restart_t=5.0, max_iter=20000,
+                              flags=P.SOLVE_GRAPHS if graphs else 0,
                               sap=P.SapParams(block=(4, 4, 4, 4), ncycles=2, nmr=5, storage=storage))
 
     ctx = P.Context(0)
@@ -266,7 +267,7 @@ def serve(args):
         while i < len(reqs) and reqs[i]["arrival"] <= now:
             r = reqs[i]
             tk = srv.submit(SERVE_LATTICES[r["lattice"]], (4, 4, 4, 4), r["m0"], fields[r["lattice"]], r["b"],
-                            params(P.DW_PREC_F16))
+                            params(P.DW_PREC_F16, graphs=args.serve_graphs))
             pending[tk] = i
             i += 1
         for tk in list(pending):
@@ -294,7 +295,7 @@ def serve(args):
         torch.cuda.synchronize()
         ts = time.perf_counter()
         f = P.Field(ctx, L, (4, 4, 4, 4), fields[r["lattice"]])
-        _, st = f.solve(r["m0"], params(P.DW_PREC_F64), r["b"], raise_on_notconv=False)
+        _, st = f.solve(r["m0"], params(P.DW_PREC_F64, graphs=False), r["b"], raise_on_notconv=False)
         f.close()
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - ts)
@@ -313,7 +314,7 @@ def serve(args):
         "config": {"workload": f"{len(reqs)} requests, exponential gaps mean {args.mean_gap * 1e3:.0f} ms (seed 20), "
                                f"lattices {names} uniform, nrhs 1..{args.max_rhs}, eps=0.6 links, "
                                f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s=2 nMR=5, FGMRES-DR(30,12), tol 1e-10, "
-                               f"{args.slots} slots",
+                               f"{args.slots} slots" + (", captured steps" if args.serve_graphs else ""),
                    "m_c_from": {n: mc[n][1] for n in names}},
         "makespan_s": round(makespan, 3),
         "rhs_solves_per_s": round(rhs_total / makespan, 4),
@@ -349,7 +350,9 @@ def main():
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
     ap.add_argument("--max-rhs", type=int, default=4)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--serve-graphs", action="store_true",
+                    help="serving: replay captured Arnoldi steps (HIP graphs) in single-RHS requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -364,6 +367,8 @@ def main():
     import paper_1204_5463_amd as P
     import synth
 
+    # all work on one non-default stream (HIP graph capture needs one)
+    torch.cuda.set_stream(torch.cuda.Stream())
     wl = WORKLOADS[args.workload]
     L = wl["L"]
     if args.m0 is None:
@@ -398,6 +403,8 @@ def main():
                 setattr(params, key, int(val))
             elif key == "shared":
                 params.shared_defl = int(val)
+            elif key == "graphs":
+                params.flags = P.SOLVE_GRAPHS if int(val) else 0
             else:
                 raise SystemExit(f"unknown parameter {key}")
     tune = None

@@ -102,7 +102,13 @@ typedef struct sap_params {
  *              over span Z_k) and restarts with a fresh Krylov space, as in
  *              GMRES with projection; 0 = independent FGMRES-DR solves. Not
  *              in the paper; the projection cannot raise the residual.
- *   flags      reserved, pass 0. */
+ *   flags      DW_SOLVE_GRAPHS: capture each Arnoldi step (preconditioner,
+ *              operator, Gram-Schmidt and small dense kernels) as a HIP graph
+ *              the first time it runs and replay it in later cycles (fewer
+ *              launches; used for single-RHS solves on a non-default stream
+ *              with per-kernel timing off, else ignored). Other bits must be 0. */
+enum { DW_SOLVE_GRAPHS = 1 };
+
 typedef struct fgmresdr_params {
   int32_t m;
   int32_t k;

@@ -29,6 +29,7 @@ __all__ = [
 
 DW_OK, DW_EINVAL, DW_ENOMEM, DW_EHIP, DW_ENOTCONV, DW_EBUSY, DW_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 DW_PREC_F64, DW_PREC_F32, DW_PREC_F16, DW_PREC_BF16 = 0, 1, 2, 3
+SOLVE_GRAPHS = 1
 PREC_NAMES = {"f64": DW_PREC_F64, "f32": DW_PREC_F32, "f16": DW_PREC_F16, "bf16": DW_PREC_BF16}
 PAIR_BYTES = {DW_PREC_F64: 16, DW_PREC_F32: 8, DW_PREC_F16: 4, DW_PREC_BF16: 4}
 
@@ -135,13 +136,14 @@ class SolverParams:
     restart_t: float = 5.0
     sap: SapParams = dataclasses.field(default_factory=SapParams)
     shared_defl: int = 0
+    flags: int = 0          # SOLVE_GRAPHS: replay captured Arnoldi steps (single RHS, non-default stream)
 
     def _c(self):
         p = _SolverParams()
         p.m, p.k, p.max_iter, p.shared_defl = int(self.m), int(self.k), int(self.max_iter), int(self.shared_defl)
         p.tol, p.restart_t = float(self.tol), float(self.restart_t)
         p.sap = self.sap._c()
-        p.flags = p.reserved = 0
+        p.flags, p.reserved = int(self.flags), 0
         return p
 
 
@@ -498,7 +500,7 @@ class TuneSpace:
 def _params_from_c(p: _SolverParams) -> SolverParams:
     return SolverParams(m=p.m, k=p.k, max_iter=p.max_iter, tol=p.tol, restart_t=p.restart_t,
                         sap=SapParams(block=tuple(p.sap.block), ncycles=p.sap.ncycles, nmr=p.sap.nmr,
-                                      storage=p.sap.storage), shared_defl=p.shared_defl)
+                                      storage=p.sap.storage), shared_defl=p.shared_defl, flags=p.flags)
 
 
 class TuneCache:

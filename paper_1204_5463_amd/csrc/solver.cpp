@@ -55,7 +55,11 @@ struct Work {
   DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal, rlist, proj;
   double* scal_h = nullptr;  // nr x (kSclCount + 2): scalars and the pair nrm
   int* rlist_h = nullptr;
+  // captured Arnoldi steps, indexed by 2 j + lagged (single-RHS batches)
+  std::vector<hipGraphExec_t> graphs;
   ~Work() {
+    for (hipGraphExec_t g : graphs)
+      if (g) (void)hipGraphExecDestroy(g);
     if (scal_h) (void)hipHostFree(scal_h);
     if (rlist_h) (void)hipHostFree(rlist_h);
   }
@@ -159,7 +163,10 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
   const double bd_tol = 1e-14;
   auto t0 = std::chrono::steady_clock::now();
   std::vector<Rhs> R(nr);
-  bool donor_ok = false;  // RHS 0 holds a deflation space from a deflated restart
+  bool donor_ok = false;
+  // captured steps: single-RHS batches on a stream that can be captured,
+  // without per-launch event timing
+  const bool use_graphs = (P->flags & DW_SOLVE_GRAPHS) && nr == 1 && s != nullptr && !f->ctx->prof.on;  // RHS 0 holds a deflation space from a deflated restart
 
   DW_TRY(launch_pack_spinor(g, DW_PREC_F64, b_can, W.b.p, 1.0, nr, s));
   DW_CHECK_HIP(hipMemsetAsync(W.x.p, 0, (size_t)nr * n * 16, s));
@@ -206,38 +213,64 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
       if (part.empty()) break;
       DW_TRY(set_rlist(W, part, s));
       const int np = (int)part.size();
-      // z_j = M_j applied to sigma * v_j (lagged vectors scaled by their
-      // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
-      for (int r : part)
-        DW_TRY(launch_convert(DW_PREC_F64, W.Vr(r) + 2 * (long long)j * n, prec,
-                              (char*)W.vs.p + (size_t)r * n * pair_bytes(prec), sigma, n, s,
-                              R[r].lagged ? W.scalr(r) + kSclHinv : nullptr));
-      void* zacc = zprec == DW_PREC_F64 ? (void*)(W.Z.as<double>() + 2 * (long long)j * n) : W.zs.p;
-      const long long zstride = zprec == DW_PREC_F64 ? (long long)m * n : n;
-      for (int cy = 0; cy < P->sap.ncycles; ++cy)
-        for (int colour = 0; colour < 2; ++colour)
-          DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
-                                   cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, W.rlist.as<int>()));
-      if (zprec != DW_PREC_F64)
+      auto enqueue_step = [&]() -> dw_status {
+        // z_j = M_j applied to sigma * v_j (lagged vectors scaled by their
+        // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
         for (int r : part)
-          DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), DW_PREC_F64,
-                                W.Zr(r) + 2 * (long long)j * n, 1.0 / sigma, n, s));
-      // w = D z_j in FP64 on the stored z_j, all participants in one launch
-      DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.Z.as<double>() + 2 * (long long)j * n, 1.0,
-                                 f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, np, (long long)m * n, n, s,
-                                 W.rlist.as<int>()));
-      // Gram-Schmidt with delayed reorthogonalisation, per RHS
-      for (int r : part) {
-        Rhs& q = R[r];
-        double* V = W.Vr(r);
-        const int nv = q.lagged ? j : j + 1;
-        double* vj = V + 2 * (long long)j * n;
-        DW_TRY(gs_reduce(V, n, nv, q.lagged ? vj : nullptr, W.vec(W.w, r), n, W.partr(r), W.redr(r), s));
-        DW_TRY(dense_gs_coef(W.Hr(r), nv, q.lagged ? j : -1, j, q.lagged ? 1 : 0, 1, W.redr(r), W.coefr(r),
-                             W.scalr(r), bd_tol, s));
-        DW_TRY(gs_update(V, n, nv, q.lagged ? j : -1, W.vec(W.w, r), V + 2 * (long long)(j + 1) * n, W.coefr(r), n,
-                         W.partr(r), W.nrmr(r), s));
-        DW_TRY(dense_step2(W.Hr(r), j, W.nrmr(r), W.cr(r), W.scalr(r), bd_tol, s));
+          DW_TRY(launch_convert(DW_PREC_F64, W.Vr(r) + 2 * (long long)j * n, prec,
+                                (char*)W.vs.p + (size_t)r * n * pair_bytes(prec), sigma, n, s,
+                                R[r].lagged ? W.scalr(r) + kSclHinv : nullptr));
+        void* zacc = zprec == DW_PREC_F64 ? (void*)(W.Z.as<double>() + 2 * (long long)j * n) : W.zs.p;
+        const long long zstride = zprec == DW_PREC_F64 ? (long long)m * n : n;
+        for (int cy = 0; cy < P->sap.ncycles; ++cy)
+          for (int colour = 0; colour < 2; ++colour)
+            DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
+                                     cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, W.rlist.as<int>()));
+        if (zprec != DW_PREC_F64)
+          for (int r : part)
+            DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), DW_PREC_F64,
+                                  W.Zr(r) + 2 * (long long)j * n, 1.0 / sigma, n, s));
+        // w = D z_j in FP64 on the stored z_j, all participants in one launch
+        DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.Z.as<double>() + 2 * (long long)j * n, 1.0,
+                                   f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, np, (long long)m * n, n, s,
+                                   W.rlist.as<int>()));
+        // Gram-Schmidt with delayed reorthogonalisation, per RHS
+        for (int r : part) {
+          Rhs& q = R[r];
+          double* V = W.Vr(r);
+          const int nv = q.lagged ? j : j + 1;
+          double* vj = V + 2 * (long long)j * n;
+          DW_TRY(gs_reduce(V, n, nv, q.lagged ? vj : nullptr, W.vec(W.w, r), n, W.partr(r), W.redr(r), s));
+          DW_TRY(dense_gs_coef(W.Hr(r), nv, q.lagged ? j : -1, j, q.lagged ? 1 : 0, 1, W.redr(r), W.coefr(r),
+                               W.scalr(r), bd_tol, s));
+          DW_TRY(gs_update(V, n, nv, q.lagged ? j : -1, W.vec(W.w, r), V + 2 * (long long)(j + 1) * n, W.coefr(r), n,
+                           W.partr(r), W.nrmr(r), s));
+          DW_TRY(dense_step2(W.Hr(r), j, W.nrmr(r), W.cr(r), W.scalr(r), bd_tol, s));
+        }
+        return DW_OK;
+      };
+      if (use_graphs) {
+        // one HIP graph per (j, lagged): the step's launches are identical
+        // in every cycle, so each is captured once and replayed
+        const size_t key = 2 * (size_t)j + (R[part[0]].lagged ? 1 : 0);
+        if (W.graphs.size() <= key) W.graphs.resize(key + 1, nullptr);
+        if (!W.graphs[key]) {
+          hipGraph_t gr = nullptr;
+          DW_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          const dw_status es = enqueue_step();
+          const hipError_t ce = hipStreamEndCapture(s, &gr);
+          if (es != DW_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return es;
+          }
+          DW_CHECK_HIP(ce);
+          const hipError_t ie = hipGraphInstantiate(&W.graphs[key], gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          DW_CHECK_HIP(ie);
+        }
+        DW_CHECK_HIP(hipGraphLaunch(W.graphs[key], s));
+      } else {
+        DW_TRY(enqueue_step());
       }
       DW_TRY(readback(W, s));
       for (int r : part) {
@@ -375,6 +408,10 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
     return DW_EINVAL;
   }
   DW_TRY(check_sap_params(f->g, &P->sap));
+  if (P->flags & ~DW_SOLVE_GRAPHS) {
+    set_error("fgmresdr_solve: unknown flags 0x%x", (unsigned)P->flags);
+    return DW_EINVAL;
+  }
   if (P->shared_defl != 0 && P->shared_defl != 1) {
     set_error("fgmresdr_solve: shared_defl must be 0 or 1");
     return DW_EINVAL;

@@ -169,3 +169,35 @@ def test_shared_deflation_space():
     xb, _ = f.solve(m0, prm1, P.to_device(bb[2]))
     assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
     print("iterations without / with the shared space:", [s.iterations for s in s0], [s.iterations for s in s1])
+
+
+def test_graph_captured_steps_equal_eager(c1):
+    """Arnoldi steps captured as HIP graphs and replayed in later cycles give
+    bit for bit the eager solve (many short cycles, so every graph is
+    replayed many times with the host's own synchronisation in between);
+    on the default stream the flag is ignored."""
+    import torch
+    U, b, f, xo, info = c1
+    st = torch.cuda.Stream()
+    for prec in (P.DW_PREC_F16, P.DW_PREC_F64):
+        prm = _params(prec, m=8, k=3)
+        with torch.cuda.stream(st):
+            bd = P.to_device(b)
+            xe, se = f.solve(M01, prm, bd, stream=st)
+            prm.flags = P.SOLVE_GRAPHS
+            xg, sg = f.solve(M01, prm, bd, stream=st)
+            xg2, _ = f.solve(M01, prm, bd, stream=st)
+        st.synchronize()
+        assert se[0].converged and sg[0].converged and se[0].cycles > 5
+        assert se[0].iterations == sg[0].iterations
+        assert np.array_equal(xe.cpu().numpy(), xg.cpu().numpy())
+        assert np.array_equal(xe.cpu().numpy(), xg2.cpu().numpy())
+    prm = _params(P.DW_PREC_F16, m=8, k=3)
+    prm.flags = P.SOLVE_GRAPHS
+    x0, _ = f.solve(M01, prm, P.to_device(b))
+    prm.flags = 0
+    x1, _ = f.solve(M01, prm, P.to_device(b))
+    assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
+    prm.flags = 4
+    with pytest.raises(P.DwError):
+        f.solve(M01, prm, P.to_device(b))
