@@ -338,6 +338,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true", help="skip the all-FP64 comparison solve")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--skip-dslash", action="store_true", help="skip the per-precision operator timings")
+    ap.add_argument("--skip-v32", action="store_true", help="skip the FP32-basis comparison solve")
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
     ap.add_argument("--params", default=None,
                     help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4,shared=1 (exploration)")
@@ -404,7 +405,9 @@ def main():
             elif key == "shared":
                 params.shared_defl = int(val)
             elif key == "graphs":
-                params.flags = P.SOLVE_GRAPHS if int(val) else 0
+                params.flags = (params.flags & ~P.SOLVE_GRAPHS) | (P.SOLVE_GRAPHS if int(val) else 0)
+            elif key == "v32":
+                params.flags = (params.flags & ~P.SOLVE_V32) | (P.SOLVE_V32 if int(val) else 0)
             else:
                 raise SystemExit(f"unknown parameter {key}")
     tune = None
@@ -497,7 +500,7 @@ def main():
     # ---- all-FP64 comparison solve
     if not args.skip_fp64:
         p64 = P.SolverParams(m=params.m, k=params.k, tol=params.tol, restart_t=params.restart_t,
-                             max_iter=params.max_iter,
+                             max_iter=params.max_iter, flags=params.flags,
                              sap=P.SapParams(block=params.sap.block, ncycles=params.sap.ncycles, nmr=params.sap.nmr,
                                              storage=P.DW_PREC_F64))
         torch.cuda.synchronize()
@@ -510,6 +513,25 @@ def main():
         out_extra.update({"fp64_solves_per_s": round(nrhs / t64, 4),
                           "fp64_iterations": max(s.iterations for s in s64),
                           "speedup_vs_fp64": round(value * t64 / nrhs, 3)})
+    # ---- the same solve with the Krylov basis stored in FP32 (the paper's
+    # single-precision Arnoldi storage, FP64 arithmetic and explicit FP64
+    # residual at restarts); reported beside the FP64-basis value
+    if not args.skip_v32 and not (params.flags & P.SOLVE_V32):
+        p32 = P.SolverParams(m=params.m, k=params.k, tol=params.tol, restart_t=params.restart_t,
+                             max_iter=params.max_iter, flags=params.flags | P.SOLVE_V32, sap=params.sap,
+                             shared_defl=params.shared_defl)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        f.solve(m0, p32, bt)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, s32 = f.solve(m0, p32, bt)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - ts
+        log(f"[bench] FP32-basis solve: {summary(s32)}, {t32:.3f} s")
+        out_extra["fp32_basis"] = {"solves_per_s": round(nrhs / t32, 4),
+                                   "iterations": max(s.iterations for s in s32),
+                                   "true_relres": max(s.true_relres for s in s32)}
     # ---- FGMRES(m): the same solve without deflation
     if args.also_k0:
         pk0 = P.SolverParams(m=params.m, k=0, tol=params.tol, restart_t=params.restart_t,

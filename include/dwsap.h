@@ -106,8 +106,13 @@ typedef struct sap_params {
  *              operator, Gram-Schmidt and small dense kernels) as a HIP graph
  *              the first time it runs and replay it in later cycles (fewer
  *              launches; used for single-RHS solves on a non-default stream
- *              with per-kernel timing off, else ignored). Other bits must be 0. */
-enum { DW_SOLVE_GRAPHS = 1 };
+ *              with per-kernel timing off, else ignored).
+ *              DW_SOLVE_V32: store the Krylov basis V in FP32 (the arithmetic
+ *              stays FP64), which halves the Gram-Schmidt traffic; the
+ *              Arnoldi relation then holds to FP32 accuracy and the explicit
+ *              FP64 residual at every restart (Section 4.7) keeps the solve
+ *              exact. Other bits must be 0. */
+enum { DW_SOLVE_GRAPHS = 1, DW_SOLVE_V32 = 2 };
 
 typedef struct fgmresdr_params {
   int32_t m;

@@ -31,13 +31,16 @@ dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const doub
 // Gram-Schmidt with delayed reorthogonalisation (see k_blas.hip).
 // gs_reduce: out[0..2nv+3) = [V^H u | V^H w | u^H u, u^H w, w^H w] over the
 // nv final columns; u or w may be null. partials: (2 kMaxM + 5) * kBlasGrid pairs.
-dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, const double* w, long long n,
+// V and u are stored at prec_v (FP64 or FP32), w is FP64.
+dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const double* w, long long n,
                     double* partials, double* out, hipStream_t s);
 // gs_update: jcol >= 0: V_jcol <- (V_jcol - V a)/beta; w != null:
 // wout <- w - V b - c V_jcol (c only if jcol >= 0), nrm2 <- ||wout||^2.
 // coef as written by dense_gs_coef.
-dw_status gs_update(double* V, long long stride, int nv, int jcol, const double* w, double* wout, const double* coef,
-                    long long n, double* partials, double* nrm2, hipStream_t s);
+// V and wout are stored at prec_v (FP64 or FP32); with FP32 storage nrm2 is
+// the squared norm of the stored (rounded) wout.
+dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const double* w, void* wout,
+                    const double* coef, long long n, double* partials, double* nrm2, hipStream_t s);
 
 // ---- small dense FP64 (one workgroup) ---------------------------------------------
 // Scalars block written by dense_step / dense_cycle_end (doubles):

@@ -8,6 +8,8 @@
 // All reductions are two-stage with a fixed grid and a fixed summation
 // order, so results are bitwise reproducible run to run.
 // Every kernel streams each column once: they are HBM-bandwidth bound.
+#include <type_traits>
+
 #include "dw_internal.hpp"
 #include "dw_kernels.hpp"
 #include "dw_types.hpp"
@@ -166,9 +168,9 @@ __global__ void __launch_bounds__(kThreads)
 // one update sweep forms v = (u - V a) / beta and w' = w - V b - c v.
 // Partial-sum slots: [0, nv) a, [nv, 2 nv) b, 2 nv: u^H u, 2 nv + 1: u^H w,
 // 2 nv + 2: w^H w.
-template <bool HU, bool HW>
+template <bool HU, bool HW, typename SV>
 __global__ void __launch_bounds__(kThreads)
-    k_gs_reduce(const s64* __restrict__ V, long long stride, int c0, int nc, int nv, const s64* __restrict__ u,
+    k_gs_reduce(const SV* __restrict__ V, long long stride, int c0, int nc, int nv, const SV* __restrict__ u,
                 const s64* __restrict__ w, long long n, int first, s64* __restrict__ partials) {
   constexpr int NA = kGsCols;
   __shared__ double red[kThreads / kWave][2 * NA + 3][2];
@@ -238,10 +240,10 @@ __global__ void __launch_bounds__(kThreads)
 // coef: a[0..nv), b[0..nv), c (slot 2 nv), 1/beta (slot 2 nv + 1, real part).
 // HU: V_jcol <- (V_jcol - V a) / beta (in place); HW: wout <- w - V b - c V_jcol,
 // partials[block] = sum |wout|^2 over the block's elements.
-template <bool HU, bool HW>
+template <bool HU, bool HW, typename SV>
 __global__ void __launch_bounds__(kThreads)
-    k_gs_update(s64* __restrict__ V, long long stride, int nv, int jcol, const s64* __restrict__ w,
-                s64* __restrict__ wout, const s64* __restrict__ coef, long long n, s64* __restrict__ partials) {
+    k_gs_update(SV* __restrict__ V, long long stride, int nv, int jcol, const s64* __restrict__ w,
+                SV* __restrict__ wout, const s64* __restrict__ coef, long long n, s64* __restrict__ partials) {
   __shared__ cplx<double> ca[kMaxM + 1], cb[kMaxM + 1];
   __shared__ double red[kThreads / kWave];
   for (int c = threadIdx.x; c < nv; c += kThreads) {
@@ -282,7 +284,8 @@ __global__ void __launch_bounds__(kThreads)
     }
     if constexpr (HW) {
       st(wout + i, wa);
-      nrm += norm2(wa);
+      if constexpr (std::is_same<SV, s64>::value) nrm += norm2(wa);
+      else nrm += norm2(ld<double>(wout + i));  // the stored, rounded vector
     }
   }
   if constexpr (HW) {
@@ -384,13 +387,10 @@ dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const doub
 
 namespace dw {
 
-dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, const double* w, long long n,
-                    double* partials, double* out, hipStream_t s) {
-  const bool hu = u != nullptr, hw = w != nullptr;
-  if (nv < 0 || nv > kMaxM + 1 || (!hu && !hw)) {
-    set_error("gs_reduce: bad arguments");
-    return DW_EINVAL;
-  }
+template <typename SV>
+dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, const s64* wp, long long n,
+                      double* partials, double* out, hipStream_t s) {
+  const bool hu = up != nullptr, hw = wp != nullptr;
   const unsigned G = grid_for(n);
   // the columns in as few passes as possible, split evenly (u and w are
   // re-read by every pass)
@@ -400,17 +400,19 @@ dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, 
     const int c0 = q * per;
     const int nc = nv - c0 < per ? nv - c0 : per;
     KTimer kt(DW_K_DOTS, s);
-    const s64* Vp = (const s64*)V;
-    const s64 *up = (const s64*)u, *wp = (const s64*)w;
     s64* part = (s64*)partials;
     if (hu && hw)
-      hipLaunchKernelGGL((k_gs_reduce<true, true>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0, part);
+      hipLaunchKernelGGL((k_gs_reduce<true, true, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0,
+                         part);
     else if (hu)
-      hipLaunchKernelGGL((k_gs_reduce<true, false>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0, part);
+      hipLaunchKernelGGL((k_gs_reduce<true, false, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
+                         q == 0, part);
     else
-      hipLaunchKernelGGL((k_gs_reduce<false, true>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0, part);
+      hipLaunchKernelGGL((k_gs_reduce<false, true, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
+                         q == 0, part);
     DW_CHECK_LAUNCH();
-    kt.done((double)n * 16 * (nc + (hu ? 1 : 0) + (hw ? 1 : 0)), (double)n * 8 * nc * ((hu ? 1 : 0) + (hw ? 1 : 0)));
+    kt.done((double)n * (sizeof(SV) * (nc + (hu ? 1 : 0)) + (hw ? 16 : 0)),
+            (double)n * 8 * nc * ((hu ? 1 : 0) + (hw ? 1 : 0)));
   }
   KTimer kr(DW_K_REDUCE, s);
   hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 2 * nv + 3, (s64*)out, 1, 0);
@@ -419,27 +421,35 @@ dw_status gs_reduce(const double* V, long long stride, int nv, const double* u, 
   return DW_OK;
 }
 
-dw_status gs_update(double* V, long long stride, int nv, int jcol, const double* w, double* wout, const double* coef,
-                    long long n, double* partials, double* nrm2, hipStream_t s) {
-  const bool hu = jcol >= 0, hw = w != nullptr;
-  if (nv < 0 || nv > kMaxM + 1 || (!hu && !hw)) {
-    set_error("gs_update: bad arguments");
+dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const double* w, long long n,
+                    double* partials, double* out, hipStream_t s) {
+  if (nv < 0 || nv > kMaxM + 1 || (!u && !w) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
+    set_error("gs_reduce: bad arguments");
     return DW_EINVAL;
   }
+  if (prec_v == DW_PREC_F64)
+    return gs_reduce_t((const s64*)V, stride, nv, (const s64*)u, (const s64*)w, n, partials, out, s);
+  return gs_reduce_t((const s32*)V, stride, nv, (const s32*)u, (const s64*)w, n, partials, out, s);
+}
+
+template <typename SV>
+dw_status gs_update_t(SV* Vp, long long stride, int nv, int jcol, const s64* w, SV* wout, const double* coef,
+                      long long n, double* partials, double* nrm2, hipStream_t s) {
+  const bool hu = jcol >= 0, hw = w != nullptr;
   const unsigned G = grid_for(n);
   KTimer kt(DW_K_SUBCOLS, s);
-  s64* Vp = (s64*)V;
   if (hu && hw)
-    hipLaunchKernelGGL((k_gs_update<true, true>), G, kThreads, 0, s, Vp, stride, nv, jcol, (const s64*)w, (s64*)wout,
+    hipLaunchKernelGGL((k_gs_update<true, true, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
                        (const s64*)coef, n, (s64*)partials);
   else if (hu)
-    hipLaunchKernelGGL((k_gs_update<true, false>), G, kThreads, 0, s, Vp, stride, nv, jcol, (const s64*)w,
-                       (s64*)wout, (const s64*)coef, n, (s64*)partials);
+    hipLaunchKernelGGL((k_gs_update<true, false, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
+                       (const s64*)coef, n, (s64*)partials);
   else
-    hipLaunchKernelGGL((k_gs_update<false, true>), G, kThreads, 0, s, Vp, stride, nv, jcol, (const s64*)w,
-                       (s64*)wout, (const s64*)coef, n, (s64*)partials);
+    hipLaunchKernelGGL((k_gs_update<false, true, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
+                       (const s64*)coef, n, (s64*)partials);
   DW_CHECK_LAUNCH();
-  kt.done((double)n * 16 * (nv + (hu ? 2 : 0) + (hw ? 2 : 0)), (double)n * 8 * nv * ((hu ? 1 : 0) + (hw ? 1 : 0)));
+  kt.done((double)n * (sizeof(SV) * (nv + (hu ? 2 : 0) + (hw ? 1 : 0)) + (hw ? 16 : 0)),
+          (double)n * 8 * nv * ((hu ? 1 : 0) + (hw ? 1 : 0)));
   if (hw) {
     KTimer kr(DW_K_REDUCE, s);
     hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 1, (s64*)nrm2, 1, 0);
@@ -447,6 +457,17 @@ dw_status gs_update(double* V, long long stride, int nv, int jcol, const double*
     kr.done((double)G * 16, 0);
   }
   return DW_OK;
+}
+
+dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const double* w, void* wout,
+                    const double* coef, long long n, double* partials, double* nrm2, hipStream_t s) {
+  if (nv < 0 || nv > kMaxM + 1 || (jcol < 0 && !w) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
+    set_error("gs_update: bad arguments");
+    return DW_EINVAL;
+  }
+  if (prec_v == DW_PREC_F64)
+    return gs_update_t((s64*)V, stride, nv, jcol, (const s64*)w, (s64*)wout, coef, n, partials, nrm2, s);
+  return gs_update_t((s32*)V, stride, nv, jcol, (const s64*)w, (s32*)wout, coef, n, partials, nrm2, s);
 }
 
 }  // namespace dw

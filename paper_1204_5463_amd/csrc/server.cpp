@@ -24,7 +24,7 @@
 #include "dw_internal.hpp"
 
 namespace dw {
-size_t solver_bytes(long long sites, int m, int prec, int nrhs);
+size_t solver_bytes(long long sites, int m, int prec, int flags, int nrhs);
 }
 
 using namespace dw;
@@ -150,7 +150,7 @@ size_t dw_request_footprint(const dw_request* q) {
   const int prec = q->params.sap.storage;
   if (prec < 0 || prec > 3 || q->params.m < 1 || q->params.m > 48) return 0;
   const size_t links = (size_t)g.V * 36 * (16 + 8 + 4 + 4);
-  return links + solver_bytes(g.V, q->params.m, prec, q->nrhs);
+  return links + solver_bytes(g.V, q->params.m, prec, q->params.flags, q->nrhs);
 }
 
 dw_status dw_server_create(dw_ctx ctx, const dw_server_params* p, dw_server* out) {

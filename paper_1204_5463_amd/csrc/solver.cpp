@@ -63,7 +63,10 @@ struct Work {
     if (scal_h) (void)hipHostFree(scal_h);
     if (rlist_h) (void)hipHostFree(rlist_h);
   }
-  double* Vr(int r) const { return V.as<double>() + 2 * (long long)r * (m + 1) * n; }
+  int vprec = DW_PREC_F64;  // storage of the Krylov basis V
+  // basis of RHS r, and its column j
+  void* Vr(int r) const { return (char*)V.p + (size_t)r * (m + 1) * n * pair_bytes(vprec); }
+  void* Vc(int r, int j) const { return (char*)Vr(r) + (size_t)j * n * pair_bytes(vprec); }
   double* Zr(int r) const { return Z.as<double>() + 2 * (long long)r * m * n; }
   double* vec(const DevBuf& d, int r) const { return d.as<double>() + 2 * (long long)r * n; }
   double* Hr(int r) const { return H.as<double>() + 2 * (long long)r * kLd * kMaxM; }
@@ -81,9 +84,11 @@ struct Work {
   double* projr(int r) const { return proj.as<double>() + 2 * (long long)r * (2 * kLd + kMaxM); }
 };
 
-size_t bytes_per_rhs(long long n, int m, int prec) {
+int basis_prec(const fgmresdr_params* P) { return (P->flags & DW_SOLVE_V32) ? DW_PREC_F32 : DW_PREC_F64; }
+
+size_t bytes_per_rhs(long long n, int m, int prec, int vprec) {
   const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
-  return (size_t)n * 16 * ((m + 1) + m + 4) + (size_t)n * pair_bytes(prec) +
+  return (size_t)n * pair_bytes(vprec) * (m + 1) + (size_t)n * 16 * (m + 4) + (size_t)n * pair_bytes(prec) +
          (zprec != DW_PREC_F64 ? (size_t)n * pair_bytes(zprec) : 0) + (size_t)(2 * kLd + 6) * kBlasGrid * 16;
 }
 
@@ -95,7 +100,8 @@ dw_status alloc_work(dw_field f, const fgmresdr_params* P, int nr, Work& W, hipS
   W.nr = nr;
   W.m = P->m;
   W.n = n;
-  DW_TRY(W.V.alloc(ctx, (size_t)nr * (P->m + 1) * n * 16, s));
+  W.vprec = basis_prec(P);
+  DW_TRY(W.V.alloc(ctx, (size_t)nr * (P->m + 1) * n * pair_bytes(W.vprec), s));
   DW_TRY(W.Z.alloc(ctx, (size_t)nr * P->m * n * 16, s));
   if (zprec != DW_PREC_F64) DW_TRY(W.zs.alloc(ctx, (size_t)nr * n * pair_bytes(zprec), s));
   DW_TRY(W.w.alloc(ctx, (size_t)nr * n * 16, s));
@@ -193,7 +199,10 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
       if (q.fresh) {
         // W.nrm(r) holds ||r||^2 of the current explicit residual
         DW_TRY(dense_fresh(W.Hr(r), W.cr(r), W.nrmr(r), W.scalr(r), s));
-        DW_TRY(blas_scale(W.vec(W.r, r), W.Vr(r), W.scalr(r) + kSclBetaInv, n, s));
+        if (W.vprec == DW_PREC_F64)
+          DW_TRY(blas_scale(W.vec(W.r, r), (double*)W.Vr(r), W.scalr(r) + kSclBetaInv, n, s));
+        else
+          DW_TRY(launch_convert(DW_PREC_F64, W.vec(W.r, r), W.vprec, W.Vr(r), 1.0, n, s, W.scalr(r) + kSclBetaInv));
         q.j0 = 0;
       } else {
         q.j0 = k;
@@ -217,7 +226,7 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         // z_j = M_j applied to sigma * v_j (lagged vectors scaled by their
         // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
         for (int r : part)
-          DW_TRY(launch_convert(DW_PREC_F64, W.Vr(r) + 2 * (long long)j * n, prec,
+          DW_TRY(launch_convert(W.vprec, W.Vc(r, j), prec,
                                 (char*)W.vs.p + (size_t)r * n * pair_bytes(prec), sigma, n, s,
                                 R[r].lagged ? W.scalr(r) + kSclHinv : nullptr));
         void* zacc = zprec == DW_PREC_F64 ? (void*)(W.Z.as<double>() + 2 * (long long)j * n) : W.zs.p;
@@ -237,13 +246,13 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         // Gram-Schmidt with delayed reorthogonalisation, per RHS
         for (int r : part) {
           Rhs& q = R[r];
-          double* V = W.Vr(r);
+          void* V = W.Vr(r);
           const int nv = q.lagged ? j : j + 1;
-          double* vj = V + 2 * (long long)j * n;
-          DW_TRY(gs_reduce(V, n, nv, q.lagged ? vj : nullptr, W.vec(W.w, r), n, W.partr(r), W.redr(r), s));
+          DW_TRY(gs_reduce(W.vprec, V, n, nv, q.lagged ? W.Vc(r, j) : nullptr, W.vec(W.w, r), n, W.partr(r),
+                           W.redr(r), s));
           DW_TRY(dense_gs_coef(W.Hr(r), nv, q.lagged ? j : -1, j, q.lagged ? 1 : 0, 1, W.redr(r), W.coefr(r),
                                W.scalr(r), bd_tol, s));
-          DW_TRY(gs_update(V, n, nv, q.lagged ? j : -1, W.vec(W.w, r), V + 2 * (long long)(j + 1) * n, W.coefr(r), n,
+          DW_TRY(gs_update(W.vprec, V, n, nv, q.lagged ? j : -1, W.vec(W.w, r), W.Vc(r, j + 1), W.coefr(r), n,
                            W.partr(r), W.nrmr(r), s));
           DW_TRY(dense_step2(W.Hr(r), j, W.nrmr(r), W.cr(r), W.scalr(r), bd_tol, s));
         }
@@ -288,12 +297,11 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
     // iterate and explicit FP64 residual
     for (int r : cyc) {
       Rhs& q = R[r];
-      double* V = W.Vr(r);
+      void* V = W.Vr(r);
       if (q.lagged && !q.broke) {
-        double* vl = V + 2 * (long long)q.jend * n;
-        DW_TRY(gs_reduce(V, n, q.jend, vl, nullptr, n, W.partr(r), W.redr(r), s));
+        DW_TRY(gs_reduce(W.vprec, V, n, q.jend, W.Vc(r, q.jend), nullptr, n, W.partr(r), W.redr(r), s));
         DW_TRY(dense_gs_coef(W.Hr(r), q.jend, q.jend, -1, 1, 0, W.redr(r), W.coefr(r), W.scalr(r), bd_tol, s));
-        DW_TRY(gs_update(V, n, q.jend, q.jend, nullptr, nullptr, W.coefr(r), n, W.partr(r), nullptr, s));
+        DW_TRY(gs_update(W.vprec, V, n, q.jend, q.jend, nullptr, nullptr, W.coefr(r), n, W.partr(r), nullptr, s));
       }
       DW_TRY(dense_lsq(W.Hr(r), q.jend, W.cr(r), W.etar(r), W.scalr(r), s));
       DW_TRY(blas_combine(DW_PREC_F64, W.Zr(r), n, q.jend, W.etar(r), 1.0, W.vec(W.x, r), n, s));
@@ -318,10 +326,10 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         double* t = pr;
         double* y = pr + 2 * kLd;
         double* sv = y + 2 * kMaxM;
-        DW_TRY(blas_dots(DW_PREC_F64, W.Vr(0), n, k + 1, W.vec(W.r, r), n, W.partr(r), t, 1, 0, s));
+        DW_TRY(blas_dots(W.vprec, W.Vr(0), n, k + 1, W.vec(W.r, r), n, W.partr(r), t, 1, 0, s));
         DW_TRY(dense_project(W.Hr(0), k, t, y, sv, s));
         DW_TRY(blas_combine(DW_PREC_F64, W.Zr(0), n, k, y, 1.0, W.vec(W.x, r), n, s));
-        DW_TRY(blas_combine(DW_PREC_F64, W.Vr(0), n, k + 1, sv, -1.0, W.vec(W.r, r), n, s));
+        DW_TRY(blas_combine(W.vprec, W.Vr(0), n, k + 1, sv, -1.0, W.vec(W.r, r), n, s));
       }
     }
     for (int r : cyc)
@@ -359,10 +367,10 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
           continue;
         }
         if (r == 0) donor_ok = true;
-        DW_TRY(blas_rotate(DW_PREC_F64, W.Vr(r), n, q.jend + 1, W.Qr(r), kLd, k + 1, n, s));
+        DW_TRY(blas_rotate(W.vprec, W.Vr(r), n, q.jend + 1, W.Qr(r), kLd, k + 1, n, s));
         DW_TRY(blas_rotate(DW_PREC_F64, W.Zr(r), n, q.jend, W.Qr(r), kLd, k, n, s));
         DW_CHECK_HIP(hipMemsetAsync(W.cr(r), 0, (size_t)kLd * 16, s));
-        DW_TRY(blas_dots(DW_PREC_F64, W.Vr(r), n, k + 1, W.vec(W.r, r), n, W.partr(r), W.cr(r), 1, 0, s));
+        DW_TRY(blas_dots(W.vprec, W.Vr(r), n, k + 1, W.vec(W.r, r), n, W.partr(r), W.cr(r), 1, 0, s));
         q.fresh = false;
       }
     }
@@ -388,8 +396,9 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
 }  // namespace
 
 namespace dw {
-size_t solver_bytes(long long sites, int m, int prec, int nrhs) {
-  return bytes_per_rhs(sites * 12, m, prec) * (size_t)nrhs + (size_t)nrhs * 64 * 1024;
+size_t solver_bytes(long long sites, int m, int prec, int flags, int nrhs) {
+  const int vprec = (flags & DW_SOLVE_V32) ? DW_PREC_F32 : DW_PREC_F64;
+  return bytes_per_rhs(sites * 12, m, prec, vprec) * (size_t)nrhs + (size_t)nrhs * 64 * 1024;
 }
 }  // namespace dw
 
@@ -408,7 +417,7 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
     return DW_EINVAL;
   }
   DW_TRY(check_sap_params(f->g, &P->sap));
-  if (P->flags & ~DW_SOLVE_GRAPHS) {
+  if (P->flags & ~(DW_SOLVE_GRAPHS | DW_SOLVE_V32)) {
     set_error("fgmresdr_solve: unknown flags 0x%x", (unsigned)P->flags);
     return DW_EINVAL;
   }
@@ -429,7 +438,7 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
   // RHS per batch: as many as fit in free device memory (at least one)
   size_t free_b = 0, total_b = 0;
   DW_CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t per = bytes_per_rhs(n, P->m, P->sap.storage);
+  const size_t per = bytes_per_rhs(n, P->m, P->sap.storage, basis_prec(P));
   int nb = (int)std::max<size_t>(1, (size_t)(0.9 * (double)free_b) / per);
   nb = std::min(nb, (int)nrhs);
   bool all_conv = true;

@@ -201,3 +201,21 @@ def test_graph_captured_steps_equal_eager(c1):
     prm.flags = 4
     with pytest.raises(P.DwError):
         f.solve(M01, prm, P.to_device(b))
+
+
+@pytest.mark.parametrize("prec", [P.DW_PREC_F16, P.DW_PREC_F64])
+def test_fp32_basis_reaches_fp64_residual(c1, prec):
+    """Krylov basis stored in FP32 (flag SOLVE_V32): the Arnoldi relation holds
+    to FP32 only, but the explicit FP64 residual at each restart (Section 4.7)
+    still brings the true residual to 1e-10."""
+    U, b, f, xo, info = c1
+    prm = _params(prec, m=12, k=4)
+    _, s64 = f.solve(M01, prm, P.to_device(b))
+    prm.flags = P.SOLVE_V32
+    x, st = f.solve(M01, prm, P.to_device(b))
+    x = x.cpu().numpy()
+    assert st[0].converged
+    r = b - W.apply_D(U, M01, x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert st[0].iterations <= 1.5 * s64[0].iterations + 12
