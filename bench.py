@@ -212,7 +212,8 @@ def serve(args):
     """Serving stream: exponential inter-arrivals, a mix of lattice sizes
     and RHS counts near the critical mass, solved by the library's server
     (continuous batching on concurrent streams, FP16 SAP) and, for
-    comparison, one request at a time with all-FP64 SAP in the same order
+    comparison, one request at a time with all-FP64 SAP (same SAP
+    parameters) in the same order
     (its latencies follow from the measured service times and the same
     arrival times). Prints one JSON line."""
     import numpy as np
@@ -242,10 +243,12 @@ def serve(args):
         r["b"] = P.to_device(synth.gaussian_spinors(SERVE_LATTICES[r["lattice"]], r["nrhs"], seed0=r["seed"]))
     log(f"[serve] {len(reqs)} requests over {t:.2f} s of arrivals")
 
+    # SAP parameters from the time-to-solution tuning at 32^3x64 (the flat
+    # optimum s = 6..8, nMR = 7..10), the same for every request
     def params(storage, graphs=False):
         return P.SolverParams(m=30, k=12, tol=1e-10, restart_t=5.0, max_iter=20000,
                               flags=P.SOLVE_GRAPHS if graphs else 0,
-                              sap=P.SapParams(block=(4, 4, 4, 4), ncycles=2, nmr=5, storage=storage))
+                              sap=P.SapParams(block=(4, 4, 4, 4), ncycles=6, nmr=8, storage=storage))
 
     ctx = P.Context(0)
     # warm the kernels of every lattice once (untimed)
@@ -313,7 +316,7 @@ def serve(args):
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, exponential gaps mean {args.mean_gap * 1e3:.0f} ms (seed 20), "
                                f"lattices {names} uniform, nrhs 1..{args.max_rhs}, eps=0.6 links, "
-                               f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s=2 nMR=5, FGMRES-DR(30,12), tol 1e-10, "
+                               f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s=6 nMR=8, FGMRES-DR(30,12), tol 1e-10, "
                                f"{args.slots} slots" + (", captured steps" if args.serve_graphs else ""),
                    "m_c_from": {n: mc[n][1] for n in names}},
         "makespan_s": round(makespan, 3),
