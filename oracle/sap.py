@@ -21,6 +21,10 @@ Readings of the paper taken here:
   * MR starts from y = 0, uses alpha = (p^H rho)/(p^H p) over the block's
     sites (alpha = 0 if p = 0) and no relaxation;
   * one SAP cycle = both colours once.
+
+``C`` (optional) is a site-local 12x12 term added to the operator, the
+clover term of ``oracle/clover.py``; being site-local it belongs to every
+block operator D^l whole.
 """
 from __future__ import annotations
 
@@ -74,7 +78,7 @@ def block_broadcast(s, L, block):
     return e
 
 
-def mr_blocks(U, m0, L, block, r, nmr):
+def mr_blocks(U, m0, L, block, r, nmr, C=None):
     """n_MR minimal-residual steps for D^l y^l = r^l on every block at once.
 
     ``r`` must vanish outside the blocks being solved (the hop cut of D^l
@@ -83,7 +87,7 @@ def mr_blocks(U, m0, L, block, r, nmr):
     y = np.zeros_like(r)
     rho = r.copy()
     for _ in range(nmr):
-        p = apply_D_blocks(U, m0, rho, block)
+        p = apply_D_blocks(U, m0, rho, block, C)
         num = block_sum(np.conj(p) * rho, L, block)           # p^H rho per block
         den = block_sum(np.abs(p) ** 2, L, block).real          # p^H p per block
         alpha = np.where(den > 0.0, num / np.where(den > 0.0, den, 1.0), 0.0)
@@ -93,7 +97,7 @@ def mr_blocks(U, m0, L, block, r, nmr):
     return y, rho
 
 
-def sap(U, m0, L, block, ncycles, nmr, v, block_solver=None):
+def sap(U, m0, L, block, ncycles, nmr, v, block_solver=None, C=None):
     """z = M v: ``ncycles`` SAP cycles (Alg. 2) from z = 0.
 
     Per cycle and colour: r = (v - D z) on the blocks of that colour, block
@@ -105,9 +109,9 @@ def sap(U, m0, L, block, ncycles, nmr, v, block_solver=None):
     masks = [colour_mask(L, block, c)[..., None, None] for c in (0, 1)]
     for _ in range(ncycles):
         for c in (0, 1):
-            r = (v - apply_D(U, m0, z)) * masks[c]
+            r = (v - apply_D(U, m0, z, C)) * masks[c]
             if block_solver is None:
-                y, _ = mr_blocks(U, m0, L, block, r, nmr)
+                y, _ = mr_blocks(U, m0, L, block, r, nmr, C)
             else:
                 y = block_solver(r, c) * masks[c]
             z = z + y

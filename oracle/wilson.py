@@ -84,9 +84,16 @@ def hop_backward(U, x, mu):
     return _spin_mul(P_PLUS[mu], t)
 
 
-def apply_D(U, m0, x):
-    """y = D x, eq. (1), periodic lattice."""
-    y = (4.0 + m0) * x
+def _site_term(C, x):
+    """Site-local 12x12 term (the clover term of ``oracle.clover``), or 0."""
+    if C is None:
+        return 0.0
+    return np.einsum("...satb,...tb->...sa", C, x)
+
+
+def apply_D(U, m0, x, C=None):
+    """y = D x, eq. (1), periodic lattice; plus the site-local term C x if given."""
+    y = (4.0 + m0) * x + _site_term(C, x)
     for mu in range(4):
         y = y - 0.5 * (hop_forward(U, x, mu) + hop_backward(U, x, mu))
     return y
@@ -107,7 +114,7 @@ def block_coords_masks(shape, block):
     return fwd, bwd
 
 
-def apply_D_blocks(U, m0, x, block):
+def apply_D_blocks(U, m0, x, block, C=None):
     """Block-diagonal part of D: D^l applied on every block at once (eq. 2).
 
     A hop n -> n +/- mu is kept only if both sites lie in the same block.
@@ -116,7 +123,7 @@ def apply_D_blocks(U, m0, x, block):
     """
     shape = x.shape[:4]
     fwd, bwd = block_coords_masks(shape, block)
-    y = (4.0 + m0) * x
+    y = (4.0 + m0) * x + _site_term(C, x)
     for mu in range(4):
         hf = hop_forward(U, x, mu) * fwd[mu][..., None, None]
         hb = hop_backward(U, x, mu) * bwd[mu][..., None, None]
@@ -124,7 +131,7 @@ def apply_D_blocks(U, m0, x, block):
     return y
 
 
-def apply_D_at_sites(U, m0, x, sites):
+def apply_D_at_sites(U, m0, x, sites, C=None):
     """(D x)(n) for a list of lexicographic site indices, one site at a time.
 
     A direct transcription of eq. (1) per site, used to sample outputs of
@@ -137,6 +144,8 @@ def apply_D_at_sites(U, m0, x, sites):
         s = int(s)
         c = [s % Lx, (s // Lx) % Ly, (s // (Lx * Ly)) % Lz, s // (Lx * Ly * Lz)]
         acc = (4.0 + m0) * x[c[3], c[2], c[1], c[0]]
+        if C is not None:
+            acc = acc + np.einsum("satb,tb->sa", C[c[3], c[2], c[1], c[0]], x[c[3], c[2], c[1], c[0]])
         for mu in range(4):
             f = list(c)
             f[mu] = (f[mu] + 1) % ext[mu]
@@ -151,7 +160,7 @@ def apply_D_at_sites(U, m0, x, sites):
     return out
 
 
-def dense_D(U, m0, block=None):
+def dense_D(U, m0, block=None, C=None):
     """Assemble D (or the block-diagonal part if ``block`` is given) as a dense
     matrix by applying it to every unit vector. Only for tiny lattices."""
     shape = U.shape[1:5]
@@ -161,7 +170,7 @@ def dense_D(U, m0, block=None):
     for j in range(n):
         e[j] = 1.0
         x = e.reshape(shape + (4, 3))
-        y = apply_D(U, m0, x) if block is None else apply_D_blocks(U, m0, x, block)
+        y = apply_D(U, m0, x, C) if block is None else apply_D_blocks(U, m0, x, block, C)
         M[:, j] = y.reshape(-1)
         e[j] = 0.0
     return M

@@ -1,0 +1,92 @@
+"""Pins of the oracle's clover term (``oracle/clover.py``) against facts that
+do not come from its own formulas:
+
+* free field and pure gauge: every plaquette is the identity, F = 0;
+* a constant abelian magnetic field B in the (x, y) plane: every plaquette
+  away from the x wrap is exp(iB) in the first two colours, so
+  F_xy = i sin(B) diag(1, -1, 0) and all other planes vanish;
+* sigma_xy = -diag(s3, s3) in the chiral basis (from gamma_x gamma_y = i diag(s3, s3));
+* the term is Hermitian, commutes with gamma5 (no coupling between the
+  chiralities), is gauge covariant, and D_sw stays gamma5-Hermitian.
+"""
+import numpy as np
+
+import synth
+from oracle import clover as Cl
+from oracle import wilson as W
+
+L = (4, 4, 4, 8)
+
+
+def test_free_field_and_pure_gauge_vanish():
+    U1 = synth.unit_gauge_field(L)
+    assert np.count_nonzero(Cl.clover_term(U1, 1.7)) == 0
+    Om = synth.haar_su3_field(L, 7)
+    Ug = synth.pure_gauge_field(Om)
+    assert np.max(np.abs(Cl.clover_term(Ug, 1.7))) < 1e-13
+
+
+def test_sigma_xy_closed_form():
+    s3 = np.diag([1.0, -1.0])
+    expect = -np.kron(np.eye(2), s3)
+    assert np.allclose(Cl.sigma(0, 1), expect, atol=0, rtol=0)
+
+
+def test_constant_abelian_field():
+    Lx, Ly, Lz, Lt = 8, 4, 4, 4
+    B = 0.3
+    U = synth.unit_gauge_field((Lx, Ly, Lz, Lt))
+    x = np.arange(Lx)
+    ph = np.exp(1j * B * x)
+    Uy = np.zeros((Lx, 3, 3), dtype=np.complex128)
+    Uy[:, 0, 0], Uy[:, 1, 1], Uy[:, 2, 2] = ph, np.conj(ph), 1.0
+    U[1] = np.broadcast_to(Uy, (Lt, Lz, Ly, Lx, 3, 3))
+    F = Cl.field_strength(U, 0, 1)
+    inner = F[:, :, :, 1:Lx - 1]
+    assert np.max(np.abs(inner - 1j * np.sin(B) * np.diag([1.0, -1.0, 0.0]))) < 1e-15
+    for mu, nu in [(0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]:
+        assert np.max(np.abs(Cl.field_strength(U, mu, nu))) < 1e-15
+    # the 12x12 term at an interior site: (i csw / 2) sigma_xy (x) F_xy
+    csw = 1.9
+    C = Cl.clover_term(U, csw)[0, 0, 0, 3].reshape(12, 12)
+    s = np.diag([-1.0, 1.0, -1.0, 1.0])
+    expect = (0.5j * csw) * np.kron(s, 1j * np.sin(B) * np.diag([1.0, -1.0, 0.0]))
+    assert np.max(np.abs(C - expect)) < 1e-15
+
+
+def test_hermitian_chiral_and_linear():
+    U = synth.gauge_field(L, 0.6, 3)
+    C = Cl.clover_term(U, 1.3)
+    M = C.reshape(C.shape[:4] + (12, 12))
+    assert np.max(np.abs(M - np.conj(np.swapaxes(M, -1, -2)))) < 1e-15
+    assert np.max(np.abs(M[..., :6, 6:])) == 0 and np.max(np.abs(M[..., 6:, :6])) == 0
+    assert np.allclose(Cl.clover_term(U, 2.6), 2 * C, rtol=1e-15, atol=1e-16)
+    assert np.max(np.abs(Cl.clover_term(U, 0.0))) == 0
+
+
+def test_gauge_covariance():
+    U = synth.gauge_field(L, 0.6, 4)
+    Om = synth.haar_su3_field(L, 7)
+    # U_mu(n) -> Om(n) U_mu(n) Om(n + mu)^dagger
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Ug[mu] = Om @ U[mu] @ np.conj(np.swapaxes(np.roll(Om, -1, axis=W.AXIS[mu]), -1, -2))
+    C = Cl.clover_term(U, 1.1)
+    Cg = Cl.clover_term(Ug, 1.1)
+    # C[U^Om](n) = Om(n) C[U](n) Om(n)^dagger on the colour indices
+    rot = np.einsum("...ac,...sctd,...bd->...satb", Om, C, np.conj(Om))
+    assert np.max(np.abs(Cg - rot)) < 1e-13
+
+
+def test_dsw_gamma5_hermitian():
+    U = synth.gauge_field(L, 0.6, 5)
+    C = Cl.clover_term(U, 1.5)
+    x = synth.gaussian_spinor(L, 1)
+    y = synth.gaussian_spinor(L, 2)
+    m0 = -0.3
+    lhs = W.inner(y, W.gamma5_apply(W.apply_D(U, m0, W.gamma5_apply(x), C)))
+    rhs = W.inner(W.apply_D(U, m0, y, C), x)
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+    # block operator keeps the (site-local) term
+    yb = W.apply_D_blocks(U, m0, x, (2, 2, 2, 2), C) - W.apply_D_blocks(U, m0, x, (2, 2, 2, 2))
+    assert np.max(np.abs(yb - Cl.apply_clover(C, x))) < 1e-14
