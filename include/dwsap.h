@@ -154,6 +154,17 @@ dw_status dw_ctx_destroy(dw_ctx ctx);
 dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4], const double* U_dev,
                           hipStream_t stream, dw_field* out);
 dw_status dw_field_destroy(dw_field field);
+
+/* Adds the clover (Sheikholeslami-Wohlert) term to the field's operator, as
+ * in the paper's experiments (Section 5):
+ *   D_sw = D + (i c_sw / 2) sum_{mu<nu} sigma_{mu nu} F_{mu nu}(n),
+ *   sigma_{mu nu} = (i/2)[g_mu, g_nu], F_{mu nu} = (Q_{mu nu} - Q_{mu nu}^+)/8,
+ * Q_{mu nu}(n) the four plaquettes of the (mu, nu) plane around n. The term
+ * is site-local, so it is also part of every SAP block operator. It is
+ * built on the device from the field's links (asynchronous on `stream`)
+ * and used from then on by dw_apply, dw_apply_ex, sap_precondition and
+ * fgmresdr_solve. csw = 0 removes it. DW_EINVAL: non-finite csw. */
+dw_status dw_field_set_clover(dw_field field, double csw, hipStream_t stream);
 /* Lattice sites of the field (convenience for callers sizing buffers). */
 int64_t dw_field_volume(dw_field field);
 
@@ -217,6 +228,7 @@ typedef struct dw_request {
   int32_t L[4];           /* lattice extents */
   int32_t block[4];       /* SAP block extents (params.sap.block must match) */
   double m0;              /* mass */
+  double csw;             /* clover coefficient (0: plain Wilson), see dw_field_set_clover */
   const double* U;        /* canonical gauge field, complex128 */
   int32_t nrhs;           /* right-hand sides (solved in lock-step) */
   int32_t reserved;
@@ -282,13 +294,14 @@ typedef struct dw_tune_trial {
 } dw_tune_trial;
 
 /* Tunes the solver for lattice L, gauge field U (canonical layout, device),
- * mass m0 and right-hand sides b (nrhs canonical spinors, device). x is a
+ * mass m0, clover coefficient csw (0: none) and right-hand sides b (nrhs canonical spinors, device). x is a
  * device work array of the size of b (it holds the last candidate's
  * solution). trials: host array of max_trials entries receiving every
  * candidate in the order tried; *ntrials is set to the count. *best gets
  * the fastest converged candidate (DW_ENOTCONV if none converged). Fields
  * for the candidate block shapes are created and destroyed inside. */
-dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U, double m0, const fgmresdr_params* base,
+dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U, double m0, double csw,
+                      const fgmresdr_params* base,
                       const dw_tune_space* space, const double* b, double* x, int32_t nrhs, dw_tune_trial* trials,
                       int32_t max_trials, int32_t* ntrials, fgmresdr_params* best, hipStream_t stream);
 

@@ -73,3 +73,40 @@ def clover_term(U, csw):
 def apply_clover(C, x):
     """(C x)(n)_{s a} = sum_{t b} C(n)_{s a, t b} x(n)_{t b}."""
     return np.einsum("...satb,...tb->...sa", C, x)
+
+
+def clover_at_sites(U, csw, sites):
+    """The 12x12 clover matrix at a list of lexicographic sites, computed
+    site by site from explicit link products (for lattices too large for
+    ``clover_term``). Returns [len(sites), 4, 3, 4, 3]."""
+    Lt, Lz, Ly, Lx = U.shape[1:5]
+    ext = (Lx, Ly, Lz, Lt)
+
+    def link(mu, c):
+        x, y, z, t = (c[d] % ext[d] for d in range(4))
+        return U[mu, t, z, y, x]
+
+    def step(c, mu, s):
+        c = list(c)
+        c[mu] += s
+        return c
+
+    out = np.zeros((len(sites), 4, 3, 4, 3), dtype=np.complex128)
+    for i, s in enumerate(sites):
+        s = int(s)
+        n = [s % Lx, (s // Lx) % Ly, (s // (Lx * Ly)) % Lz, s // (Lx * Ly * Lz)]
+        for mu in range(4):
+            for nu in range(mu + 1, 4):
+                a, b = step(n, mu, 1), step(n, nu, 1)
+                c = step(n, mu, -1)
+                d = step(c, nu, 1)
+                f = step(c, nu, -1)
+                h = step(n, nu, -1)
+                k = step(h, mu, 1)
+                q = link(mu, n) @ link(nu, a) @ _dag(link(mu, b)) @ _dag(link(nu, n))
+                q = q + link(nu, n) @ _dag(link(mu, d)) @ _dag(link(nu, c)) @ link(mu, c)
+                q = q + _dag(link(mu, c)) @ _dag(link(nu, f)) @ link(mu, f) @ link(nu, h)
+                q = q + _dag(link(nu, h)) @ link(mu, h) @ link(nu, k) @ _dag(link(mu, n))
+                F = (q - _dag(q)) / 8.0
+                out[i] += (0.5j * csw) * np.einsum("st,ab->satb", sigma(mu, nu), F)
+    return out

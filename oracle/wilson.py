@@ -135,7 +135,8 @@ def apply_D_at_sites(U, m0, x, sites, C=None):
     """(D x)(n) for a list of lexicographic site indices, one site at a time.
 
     A direct transcription of eq. (1) per site, used to sample outputs of
-    lattices too large for a whole-field comparison.
+    lattices too large for a whole-field comparison. ``C`` (optional) holds
+    the site-local 12x12 term at those sites, in the order of ``sites``.
     """
     Lt, Lz, Ly, Lx = x.shape[:4]
     ext = (Lx, Ly, Lz, Lt)
@@ -145,7 +146,7 @@ def apply_D_at_sites(U, m0, x, sites, C=None):
         c = [s % Lx, (s // Lx) % Ly, (s // (Lx * Ly)) % Lz, s // (Lx * Ly * Lz)]
         acc = (4.0 + m0) * x[c[3], c[2], c[1], c[0]]
         if C is not None:
-            acc = acc + np.einsum("satb,tb->sa", C[c[3], c[2], c[1], c[0]], x[c[3], c[2], c[1], c[0]])
+            acc = acc + np.einsum("satb,tb->sa", C[i], x[c[3], c[2], c[1], c[0]])
         for mu in range(4):
             f = list(c)
             f[mu] = (f[mu] + 1) % ext[mu]

@@ -79,7 +79,8 @@ class _ServerParams(ctypes.Structure):
 
 class _Request(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32 * 4), ("block", ctypes.c_int32 * 4), ("m0", ctypes.c_double),
-                ("U", ctypes.c_void_p), ("nrhs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("csw", ctypes.c_double), ("U", ctypes.c_void_p), ("nrhs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
                 ("b", ctypes.c_void_p), ("x", ctypes.c_void_p), ("params", _SolverParams)]
 
 
@@ -176,6 +177,7 @@ def load(path: str = LIB_PATH):
         "dw_ctx_destroy": (st, [vp]),
         "dw_field_create": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, ctypes.POINTER(vp)]),
         "dw_field_destroy": (st, [vp]),
+        "dw_field_set_clover": (st, [vp, dbl, vp]),
         "dw_field_volume": (i64, [vp]),
         "dw_apply": (st, [vp, dbl, vp, vp, i32, vp]),
         "dw_apply_ex": (st, [vp, dbl, i32, vp, vp, i32, vp]),
@@ -193,7 +195,7 @@ def load(path: str = LIB_PATH):
         "solve_submit": (st, [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]),
         "solve_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(_Stats),
                             ctypes.POINTER(_ReqTimes)]),
-        "dw_autotune": (st, [vp, ctypes.POINTER(i32), vp, dbl, ctypes.POINTER(_SolverParams),
+        "dw_autotune": (st, [vp, ctypes.POINTER(i32), vp, dbl, dbl, ctypes.POINTER(_SolverParams),
                              ctypes.POINTER(_TuneSpace), vp, vp, i32, ctypes.POINTER(_TuneTrial), i32,
                              ctypes.POINTER(i32), ctypes.POINTER(_SolverParams), vp]),
     }
@@ -306,6 +308,12 @@ class Field:
         self.volume = int(lib().dw_field_volume(h))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
 
+    def set_clover(self, csw: float, stream=None):
+        """Add the clover term with coefficient csw (0 removes it); see dw_field_set_clover."""
+        _check(lib().dw_field_set_clover(self.handle, float(csw), _stream(stream)), "dw_field_set_clover")
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        self.csw = float(csw)
+
     def close(self):
         if getattr(self, "handle", None):
             lib().dw_field_destroy(self.handle)
@@ -381,7 +389,7 @@ class Field:
         return x, stats
 
 
-def _request(L, block, m0, U, b, x, params: SolverParams):
+def _request(L, block, m0, U, b, x, params: SolverParams, csw=0.0):
     Lx, Ly, Lz, Lt = (int(v) for v in L)
     if tuple(U.shape) != (4, Lt, Lz, Ly, Lx, 3, 3):
         raise ValueError(f"gauge shape {tuple(U.shape)} does not match L={tuple(L)}")
@@ -392,7 +400,7 @@ def _request(L, block, m0, U, b, x, params: SolverParams):
     r = _Request()
     for i in range(4):
         r.L[i], r.block[i] = (Lx, Ly, Lz, Lt)[i], int(block[i])
-    r.m0, r.nrhs, r.reserved = float(m0), nrhs, 0
+    r.m0, r.csw, r.nrhs, r.reserved = float(m0), float(csw), nrhs, 0
     r.U, r.b, r.x = _dev_ptr(U), _dev_ptr(b), _dev_ptr(x)
     r.params = params._c()
     return r
@@ -416,15 +424,15 @@ class Server:
         self._live = {}
 
     @staticmethod
-    def footprint(L, block, m0, U, b, params: SolverParams, x=None):
-        r = _request(L, block, m0, U, b, b if x is None else x, params)
+    def footprint(L, block, m0, U, b, params: SolverParams, x=None, csw=0.0):
+        r = _request(L, block, m0, U, b, b if x is None else x, params, csw)
         return int(lib().dw_request_footprint(ctypes.byref(r)))
 
     def submit(self, L, block, m0: float, U: torch.Tensor, b: torch.Tensor, params: SolverParams,
-               x: torch.Tensor | None = None):
+               x: torch.Tensor | None = None, csw: float = 0.0):
         if x is None:
             x = torch.empty_like(b)
-        r = _request(L, block, m0, U, b, x, params)
+        r = _request(L, block, m0, U, b, x, params, csw)
         torch.cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
         _check(lib().solve_submit(self.handle, ctypes.byref(r), ctypes.byref(t)), "solve_submit")
@@ -545,7 +553,8 @@ class TuneCache:
 
 
 def autotune(ctx: Context, L, U: torch.Tensor, m0: float, base: SolverParams, b: torch.Tensor,
-             space: TuneSpace | None = None, cache: TuneCache | None = None, max_trials: int = 64, stream=None):
+             space: TuneSpace | None = None, cache: TuneCache | None = None, max_trials: int = 64, stream=None,
+             csw: float = 0.0):
     """Tune (block, nmr, s, m, k) by time to solution (dw_autotune). Returns
     (best SolverParams, list of trial dicts); with a cache, a stored result is
     returned without solving (trials then empty)."""
@@ -557,7 +566,7 @@ def autotune(ctx: Context, L, U: torch.Tensor, m0: float, base: SolverParams, b:
     key = None
     if cache is not None:
         arch = torch.cuda.get_device_properties(b.device).gcnArchName
-        key = TuneCache.key(arch, L, m0, base, nrhs)
+        key = TuneCache.key(arch, L, m0, base, nrhs) + (f"|csw={float(csw):.6f}" if csw else "")
         hit = cache.get(key)
         if hit is not None:
             return hit, []
@@ -567,7 +576,7 @@ def autotune(ctx: Context, L, U: torch.Tensor, m0: float, base: SolverParams, b:
     nt = ctypes.c_int32()
     best = _SolverParams()
     bp, sp = base._c(), space._c()
-    _check(lib().dw_autotune(ctx.handle, La, _dev_ptr(U), float(m0), ctypes.byref(bp), ctypes.byref(sp),
+    _check(lib().dw_autotune(ctx.handle, La, _dev_ptr(U), float(m0), float(csw), ctypes.byref(bp), ctypes.byref(sp),
                              _dev_ptr(b), _dev_ptr(x), nrhs, tr, int(max_trials), ctypes.byref(nt),
                              ctypes.byref(best), _stream(stream)), "dw_autotune")
     trials = []

@@ -38,6 +38,8 @@ struct dw_field_s {
   dw_ctx ctx;
   dw::Geom g;
   void* U[4];  // links per dw_prec, internal layout
+  void* C[4];  // clover term per dw_prec (null without one)
+  double csw;
   hipStream_t stream;  // stream the field was created on (its memory is freed there)
 };
 
@@ -135,6 +137,13 @@ dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* ou
 dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* out, double scale, int nrhs,
                                hipStream_t s);
 dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out, hipStream_t s);
+// sigma_{mu nu} chirality blocks (2x2) for the six planes mu < nu
+struct SigmaBlocks {
+  double re[6][2][4], im[6][2][4];
+};
+SigmaBlocks sigma_blocks();
+// clover term (FP64, packed per dw_clover.hpp) from the FP64 internal links
+dw_status launch_clover_build(const Geom& g, const void* U64, double csw, double* out, hipStream_t s);
 // elementwise out = scale * (dscale ? dscale[0] : 1) * in over n pairs
 // (precision conversion; dscale is a device scalar)
 dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s,
@@ -146,15 +155,16 @@ dw_status launch_convert(int pin, const void* in, int pout, void* out, double sc
 // rlist (device, may be null): the nrhs right-hand-side indices to process.
 dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
                               double* y, const double* b, int mode, int nrhs, long long x_rhs_stride,
-                              long long y_rhs_stride, hipStream_t s, const int* rlist = nullptr);
+                              long long y_rhs_stride, hipStream_t s, const int* rlist = nullptr,
+                              const void* C64 = nullptr);
 dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
-                             hipStream_t s);
+                             hipStream_t s, const void* C = nullptr);
 
 // One SAP colour sweep: for every block of `colour`, r = v - D z on the
 // block, nmr MR steps on D^l y = r, z += y. v at storage precision `prec`,
 // z at FP64 (prec F64) or FP32 (otherwise). z_zero: z is zero on entry.
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
                             int nmr, int z_zero, int nrhs, long long v_rhs_stride, long long z_rhs_stride,
-                            hipStream_t s, const int* rlist = nullptr);
+                            hipStream_t s, const int* rlist = nullptr, const void* C = nullptr);
 
 }  // namespace dw

@@ -15,6 +15,7 @@
 // one spinor read, 4 links read and one spinor write (FP64: 960 bytes). The
 // result is written with streaming stores (it is not read again by this
 // launch), which leaves more of the caches to the block faces.
+#include "dw_clover.hpp"
 #include "dw_internal.hpp"
 #include "dw_stencil.hpp"
 
@@ -94,10 +95,12 @@ __device__ __forceinline__ void blk_dir(const BlkCtx<T, SX, SG>& c, cplx<T> acc[
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-template <typename T, typename SX, typename SG, typename SY, int MODE, int MAXT>
+// CLOV: add the clover term (site-local, dw_clover.hpp) from Cl.
+template <typename T, typename SX, typename SG, typename SY, int MODE, int MAXT, bool CLOV>
 __global__ void __launch_bounds__(MAXT)
     k_dslash_blk(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
-                 const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist) {
+                 const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist,
+                 const SG* __restrict__ Cl) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   SX* xsh = reinterpret_cast<SX*>(smem);
   cplx<T>* pb = reinterpret_cast<cplx<T>*>(smem + align16((size_t)12 * g.bvol * sizeof(SX)));
@@ -136,6 +139,15 @@ __global__ void __launch_bounds__(MAXT)
   blk_dir<3>(c, acc, psi);
   if (active) {
     const T half = (T)0.5;
+    if constexpr (CLOV) {
+      // acc holds the hop sum; -1/2 acc + C psi = -1/2 (acc - 2 C psi)
+      cplx<T> cx[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) cx[k] = mk<T>(0, 0);
+      clover_acc<T>(Cl + (long long)b * kCloverPairs * g.bvol, g.bvol, l, psi, cx);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] -= (T)2 * cx[k];
+    }
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const long long idx = spinor_index(g, b, k, l);
@@ -153,10 +165,11 @@ size_t blk_lds(const Geom& g) {
 
 // ---- gather kernel (blocks too large for LDS staging) -------------------------------
 // MODE 0: y = scale * D x ; MODE 1: y = b - scale * D x
-template <typename T, typename SX, typename SG, typename SY, int MODE>
+template <typename T, typename SX, typename SG, typename SY, int MODE, bool CLOV>
 __global__ void __launch_bounds__(kThreads)
     k_dslash(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
-             const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist) {
+             const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist,
+             const SG* __restrict__ Cl) {
   const int chunk = xcd_remap(blockIdx.x, (int)((g.V + kThreads - 1) / kThreads));
   if (chunk < 0) return;
   const long long s = (long long)chunk * kThreads + threadIdx.x;
@@ -173,6 +186,17 @@ __global__ void __launch_bounds__(kThreads)
   hop_sum_lattice<T>(g, b, l, bc, lc, U,
                      [&](int nb, int nl, int comp) { return ld<T>(xr + spinor_index(g, nb, comp, nl)); }, acc);
   const T half = (T)0.5;
+  if constexpr (CLOV) {
+    cplx<T> xo[12], cx[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      xo[c] = ld<T>(xr + spinor_index(g, b, c, l));
+      cx[c] = mk<T>(0, 0);
+    }
+    clover_acc<T>(Cl + (long long)b * kCloverPairs * g.bvol, g.bvol, l, xo, cx);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] -= (T)2 * cx[c];
+  }
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
     const long long idx = spinor_index(g, b, c, l);
@@ -186,17 +210,17 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-template <typename T, typename SX, typename SG, typename SY, int MODE>
+template <typename T, typename SX, typename SG, typename SY, int MODE, bool CLOV>
 dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                     long long ys, int nrhs, const int* rlist, hipStream_t s);
+                     long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl);
 
 dim3 grid_for(const Geom& g, int nrhs) {
   return dim3((unsigned)xcd_grid((int)((g.V + kThreads - 1) / kThreads)), (unsigned)nrhs);
 }
 
-template <typename T, typename SX, typename SG, typename SY, int MODE>
+template <typename T, typename SX, typename SG, typename SY, int MODE, bool CLOV>
 dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                     long long ys, int nrhs, const int* rlist, hipStream_t s) {
+                     long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl) {
   const size_t lds = blk_lds<T, SX>(g);
   const int threads = ((g.bvol + 63) / 64) * 64;
   if (lds <= 160 * 1024) {
@@ -209,77 +233,88 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
         }
       }
       dim3 grid((unsigned)xcd_grid(g.nblk * nrhs), 1);
-      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist);
+      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, Cl);
       DW_CHECK_LAUNCH();
       return DW_OK;
     };
-    if (threads <= 256) return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 256>);
-    if (threads <= 512) return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 512>);
-    return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 1024>);
+    if (threads <= 256) return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 256, CLOV>);
+    if (threads <= 512) return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 512, CLOV>);
+    return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 1024, CLOV>);
   }
-  hipLaunchKernelGGL((k_dslash<T, SX, SG, SY, MODE>), grid_for(g, nrhs), kThreads, 0, s, g, diag, x, scale, U, y, b,
-                     xs, ys, nrhs, rlist);
+  hipLaunchKernelGGL((k_dslash<T, SX, SG, SY, MODE, CLOV>), grid_for(g, nrhs), kThreads, 0, s, g, diag, x, scale, U,
+                     y, b, xs, ys, nrhs, rlist, Cl);
   DW_CHECK_LAUNCH();
   return DW_OK;
+}
+
+// dispatch on the presence of a clover term
+template <typename T, typename SX, typename SG, typename SY, int MODE>
+dw_status launch_c(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
+                   long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl) {
+  if (Cl) return launch_any<T, SX, SG, SY, MODE, true>(g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, s, Cl);
+  return launch_any<T, SX, SG, SY, MODE, false>(g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, s, Cl);
 }
 
 }  // namespace
 
 dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
                               double* y, const double* b, int mode, int nrhs, long long xs, long long ys,
-                              hipStream_t s, const int* rlist) {
+                              hipStream_t s, const int* rlist, const void* C64) {
   if (nrhs < 1) return DW_OK;
   const double diag = 4.0 + m0;
   const s64* Ug = (const s64*)U64;
+  const s64* Cg = (const s64*)C64;
   s64* yo = (s64*)y;
   const s64* bo = (const s64*)b;
   KTimer kt(DW_K_DSLASH_F64, s);
   dw_status st;
   if (prec_x == DW_PREC_F64) {
     const s64* xi = (const s64*)x;
-    st = mode == 0 ? launch_any<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s)
-                   : launch_any<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s);
+    st = mode == 0 ? launch_c<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg)
+                   : launch_c<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg);
   } else if (prec_x == DW_PREC_F32) {
     const s32* xi = (const s32*)x;
-    st = mode == 0 ? launch_any<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s)
-                   : launch_any<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s);
+    st = mode == 0 ? launch_c<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg)
+                   : launch_c<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg);
   } else {
     set_error("outer dslash input precision must be F64 or F32");
     return DW_EINVAL;
   }
   DW_TRY(st);
-  kt.done((double)g.V * nrhs * (12.0 * pair_bytes(prec_x) + 36 * 16 + 12 * 16 + (mode == 1 ? 12 * 16 : 0)),
-          (double)g.V * nrhs * kFlopsPerSite);
+  kt.done((double)g.V * nrhs *
+              (12.0 * pair_bytes(prec_x) + 36 * 16 + 12 * 16 + (mode == 1 ? 12 * 16 : 0) + (Cg ? kCloverPairs * 16 : 0)),
+          (double)g.V * nrhs * (kFlopsPerSite + (Cg ? kCloverFlops : 0.0)));
   return DW_OK;
 }
 
 dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
-                             hipStream_t s) {
+                             hipStream_t s, const void* C) {
   const long long sd = g.V * 12;
   KTimer kt(DW_K_DSLASH_LOWP, s);
   dw_status st;
   const float df = (float)(4.0 + m0);
   switch (prec) {
     case DW_PREC_F64:
-      st = launch_any<double, s64, s64, s64, 0>(g, 4.0 + m0, (const s64*)x, 1.0, (const s64*)U, (s64*)y, nullptr, sd,
-                                                sd, nrhs, nullptr, s);
+      st = launch_c<double, s64, s64, s64, 0>(g, 4.0 + m0, (const s64*)x, 1.0, (const s64*)U, (s64*)y, nullptr, sd,
+                                              sd, nrhs, nullptr, s, (const s64*)C);
       break;
     case DW_PREC_F32:
-      st = launch_any<float, s32, s32, s32, 0>(g, df, (const s32*)x, 1.0f, (const s32*)U, (s32*)y, nullptr, sd, sd,
-                                               nrhs, nullptr, s);
+      st = launch_c<float, s32, s32, s32, 0>(g, df, (const s32*)x, 1.0f, (const s32*)U, (s32*)y, nullptr, sd, sd,
+                                             nrhs, nullptr, s, (const s32*)C);
       break;
     case DW_PREC_F16:
-      st = launch_any<float, s16, s16, s16, 0>(g, df, (const s16*)x, 1.0f, (const s16*)U, (s16*)y, nullptr, sd, sd,
-                                               nrhs, nullptr, s);
+      st = launch_c<float, s16, s16, s16, 0>(g, df, (const s16*)x, 1.0f, (const s16*)U, (s16*)y, nullptr, sd, sd,
+                                             nrhs, nullptr, s, (const s16*)C);
       break;
     case DW_PREC_BF16:
-      st = launch_any<float, sbf, sbf, sbf, 0>(g, df, (const sbf*)x, 1.0f, (const sbf*)U, (sbf*)y, nullptr, sd, sd,
-                                               nrhs, nullptr, s);
+      st = launch_c<float, sbf, sbf, sbf, 0>(g, df, (const sbf*)x, 1.0f, (const sbf*)U, (sbf*)y, nullptr, sd, sd,
+                                             nrhs, nullptr, s, (const sbf*)C);
       break;
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_TRY(st);
-  kt.done((double)g.V * nrhs * 60.0 * pair_bytes(prec), (double)g.V * nrhs * kFlopsPerSite);
+  kt.done((double)g.V * nrhs * (60.0 + (C ? kCloverPairs : 0)) * pair_bytes(prec),
+          (double)g.V * nrhs * (kFlopsPerSite + (C ? kCloverFlops : 0.0)));
   return DW_OK;
 }
 

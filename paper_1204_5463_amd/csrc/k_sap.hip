@@ -19,6 +19,7 @@
 // by a fixed-order sum over the workgroup's waves (deterministic).
 #include <type_traits>
 
+#include "dw_clover.hpp"
 #include "dw_internal.hpp"
 #include "dw_stencil.hpp"
 
@@ -56,10 +57,13 @@ __device__ __forceinline__ T wave_sum(T a) {
 
 // BS > 0: hypercubic BS^4 blocks known at compile time (LDS offsets and
 // link strides become immediates, local coordinates bit fields).
-template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS>
+// CLOV: the operator includes the clover term Cl (site-local, dw_clover.hpp),
+// in the residual and in every MR step.
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS, bool CLOV>
 __global__ void __launch_bounds__(MAXT)
     k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
-                 int nmr, int z_zero, long long vs, long long zs, int nr, const int* __restrict__ rlist) {
+                 int nmr, int z_zero, long long vs, long long zs, int nr, const int* __restrict__ rlist,
+                 const SG* __restrict__ Cl) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int bvol = BS > 0 ? BS * BS * BS * BS : g.bvol;
   // LDS: [links 36 x bvol (LDSL)] [rho 12 x bvol] [reduction 2 x nw x 3]
@@ -136,6 +140,18 @@ __global__ void __launch_bounds__(MAXT)
       hop_sum_staged<T, true, LK, BS>(
           g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
           [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); }, u_halo, acc);
+      if constexpr (CLOV) {
+        // -1/2 hops + C z = -1/2 (hops - 2 C z)
+        cplx<T> zo[12], cz[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          zo[c] = rho_s[c * bvol + l];
+          cz[c] = mk<T>(0, 0);
+        }
+        clover_acc<T>(Cl + (long long)b * kCloverPairs * bvol, bvol, l, zo, cz);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] -= (T)2 * cz[c];
+      }
 #pragma unroll
       for (int c = 0; c < 12; ++c)
         acc[c] = ld<T>(vb + c * bvol + l) - diag * rho_s[c * bvol + l] + half * acc[c];
@@ -163,6 +179,22 @@ __global__ void __launch_bounds__(MAXT)
         hop_sum_staged<T, false, LK, BS>(
             g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
             [&](int, int, int) { return mk<T>(0, 0); }, u_halo, p);
+      if constexpr (CLOV) {
+        // the clover entries are re-read every MR step: an offset the
+        // compiler cannot see through keeps their loads inside the loop
+        // (hoisted, they would hold 72 registers)
+        int cofs = 0;
+        asm volatile("" : "+v"(cofs));
+        cplx<T> ro[12], cr[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          ro[c] = rho_s[c * bvol + l];
+          cr[c] = mk<T>(0, 0);
+        }
+        clover_acc<T>(Cl + (long long)b * kCloverPairs * bvol + cofs, bvol, l, ro, cr);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] -= (T)2 * cr[c];
+      }
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const cplx<T> r = rho_s[c * bvol + l];
@@ -215,9 +247,9 @@ __global__ void __launch_bounds__(MAXT)
   }
 }
 
-template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS = 0>
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS, bool CLOV>
 dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
   const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
   const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
   constexpr bool P16 = std::is_same<SG, s16>::value && std::is_same<T, float>::value;
@@ -228,7 +260,7 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
     return DW_EINVAL;
   }
   if (shmem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS, CLOV>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) {
       set_error("hipFuncSetAttribute(LDS %zu bytes) failed: %s", shmem, hipGetErrorString(e));
@@ -237,8 +269,9 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
   }
   dim3 grid((unsigned)xcd_grid(g.nbc * nrhs), 1);
   KTimer kt(DW_K_SAP, s);
-  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS>), grid, threads, shmem, s, g, colour, (T)(4.0 + m0),
-                     (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs, nrhs, rlist);
+  hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS, CLOV>), grid, threads, shmem, s, g, colour,
+                     (T)(4.0 + m0), (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs, nrhs, rlist,
+                     (const SG*)C);
   DW_CHECK_LAUNCH();
   // algorithmic traffic per site of this colour: v, 4 links, z read (or the
   // other colour's z cleared) and z written; flops: block residual stencil
@@ -247,14 +280,15 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
   for (int mu = 0; mu < 4; ++mu) kept += 2.0 * (g.B[mu] - 1) / g.B[mu];
   const double sites = (double)g.nbc * g.bvol * nrhs;
   const double sv = sizeof(SV), sz = sizeof(SZ), sg = sizeof(SG);
-  kt.done(sites * (12 * sv + 36 * sg + 24 * sz),
-          sites * ((z_zero ? 0.0 : 1368.0) + nmr * (48.0 + 168.0 * kept + 336.0)));
+  const double csteps = CLOV ? nmr + (z_zero ? 0 : 1) : 0;
+  kt.done(sites * (12 * sv + 36 * sg + 24 * sz + (CLOV ? kCloverPairs * sg : 0)),
+          sites * ((z_zero ? 0.0 : 1368.0) + nmr * (48.0 + 168.0 * kept + 336.0) + csteps * kCloverFlops));
   return DW_OK;
 }
 
-template <typename T, typename SV, typename SZ, typename SG, int MAXT>
+template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool CLOV>
 dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
   // Stage the block's links in LDS only when that keeps several workgroups
   // per CU: the MR steps are VALU bound and lose more to lower occupancy
   // than they gain from fewer cached link reads (measured on 4^4 blocks
@@ -263,31 +297,47 @@ dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void*
   const bool hyper4 = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4;
   if constexpr (MAXT == 256)
     if (hyper4 && need > 40 * 1024)
-      return launch_t<T, SV, SZ, SG, 256, false, 4>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+      return launch_t<T, SV, SZ, SG, 256, false, 4, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s,
+                                                          C);
   if (need <= 40 * 1024)
-    return launch_t<T, SV, SZ, SG, MAXT, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
-  return launch_t<T, SV, SZ, SG, MAXT, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+    return launch_t<T, SV, SZ, SG, MAXT, true, 0, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s,
+                                                        C);
+  return launch_t<T, SV, SZ, SG, MAXT, false, 0, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s,
+                                                       C);
+}
+
+template <typename T, typename SV, typename SZ, typename SG, bool CLOV>
+dw_status launch_b(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
+  if (g.bvol <= 256)
+    return launch_m<T, SV, SZ, SG, 256, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+  if (g.bvol <= 512)
+    return launch_m<T, SV, SZ, SG, 512, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+  return launch_m<T, SV, SZ, SG, 1024, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
 }
 
 template <typename T, typename SV, typename SZ, typename SG>
 dw_status launch(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                 int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s) {
-  if (g.bvol <= 256) return launch_m<T, SV, SZ, SG, 256>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
-  if (g.bvol <= 512) return launch_m<T, SV, SZ, SG, 512>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
-  return launch_m<T, SV, SZ, SG, 1024>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+                 int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
+  if (C) return launch_b<T, SV, SZ, SG, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+  return launch_b<T, SV, SZ, SG, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
 }
 
 }  // namespace
 
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
                             int nmr, int z_zero, int nrhs, long long vs, long long zs, hipStream_t s,
-                            const int* rlist) {
+                            const int* rlist, const void* C) {
   if (nrhs < 1) return DW_OK;
   switch (prec) {
-    case DW_PREC_F64: return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
-    case DW_PREC_F32: return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
-    case DW_PREC_F16: return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
-    case DW_PREC_BF16: return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s);
+    case DW_PREC_F64:
+      return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+    case DW_PREC_F32:
+      return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+    case DW_PREC_F16:
+      return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+    case DW_PREC_BF16:
+      return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
 }

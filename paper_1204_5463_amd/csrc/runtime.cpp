@@ -4,9 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <new>
 #include <string>
 
+#include "dw_clover.hpp"
 #include "dw_internal.hpp"
 #include "dw_kernels.hpp"
 #include <math.h>
@@ -124,7 +126,8 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
   f->ctx = ctx;
   f->g = g;
   f->stream = stream;
-  for (int p = 0; p < 4; ++p) f->U[p] = nullptr;
+  f->csw = 0.0;
+  for (int p = 0; p < 4; ++p) f->U[p] = f->C[p] = nullptr;
   for (int p = 0; p < 4; ++p) {
     size_t bytes = (size_t)g.V * 36 * pair_bytes(p);
     f->U[p] = dev_alloc(ctx, bytes, stream);
@@ -148,8 +151,44 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
 dw_status dw_field_destroy(dw_field f) {
   clear_error();
   if (!f) return DW_OK;
-  for (int p = 0; p < 4; ++p) dev_free(f->ctx, f->U[p], f->stream);
+  for (int p = 0; p < 4; ++p) {
+    dev_free(f->ctx, f->U[p], f->stream);
+    dev_free(f->ctx, f->C[p], f->stream);
+  }
   delete f;
+  return DW_OK;
+}
+
+dw_status dw_field_set_clover(dw_field f, double csw, hipStream_t stream) {
+  clear_error();
+  if (!f || !std::isfinite(csw)) {
+    set_error("dw_field_set_clover: invalid argument");
+    return DW_EINVAL;
+  }
+  DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
+  for (int p = 0; p < 4; ++p) {
+    dev_free(f->ctx, f->C[p], stream);
+    f->C[p] = nullptr;
+  }
+  f->csw = csw;
+  if (csw == 0.0) return DW_OK;
+  const long long n = f->g.V * kCloverPairs;
+  for (int p = 0; p < 4; ++p) {
+    const size_t bytes = (size_t)n * pair_bytes(p);
+    f->C[p] = dev_alloc(f->ctx, bytes, stream);
+    if (!f->C[p]) {
+      for (int q = 0; q < p; ++q) {
+        dev_free(f->ctx, f->C[q], stream);
+        f->C[q] = nullptr;
+      }
+      f->csw = 0.0;
+      set_error("dw_field_set_clover: allocation of %zu bytes failed", bytes);
+      return DW_ENOMEM;
+    }
+  }
+  DW_TRY(launch_clover_build(f->g, f->U[DW_PREC_F64], csw, (double*)f->C[DW_PREC_F64], stream));
+  for (int p = 1; p < 4; ++p) DW_TRY(launch_convert(DW_PREC_F64, f->C[DW_PREC_F64], p, f->C[p], 1.0, n, stream));
   return DW_OK;
 }
 
@@ -180,7 +219,7 @@ dw_status dw_apply(dw_field f, double m0, const double* x, double* y, int32_t nr
   DW_TRY(yi.alloc(f->ctx, n * 16 * nrhs, stream));
   DW_TRY(launch_pack_spinor(g, DW_PREC_F64, x, xi.p, 1.0, nrhs, stream));
   DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, xi.p, 1.0, f->U[DW_PREC_F64], yi.as<double>(), nullptr, 0, nrhs,
-                             (long long)n, (long long)n, stream));
+                             (long long)n, (long long)n, stream, nullptr, f->C[DW_PREC_F64]));
   DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, yi.p, y, 1.0, nrhs, stream));
   DW_CHECK_HIP(hipStreamSynchronize(stream));
   return DW_OK;
@@ -195,7 +234,7 @@ dw_status dw_apply_ex(dw_field f, double m0, int32_t prec, const void* x, void* 
   if (nrhs == 0) return DW_OK;
   DW_TRY(check_device(f->ctx));
   ProfScope ps(f->ctx);
-  return launch_dslash_lowp(f->g, m0, prec, x, f->U[prec], y, nrhs, stream);
+  return launch_dslash_lowp(f->g, m0, prec, x, f->U[prec], y, nrhs, stream, f->C[prec]);
 }
 
 dw_status dw_pack(dw_field f, int32_t prec, const double* x, void* xi, int32_t nrhs, hipStream_t stream) {
@@ -254,7 +293,7 @@ dw_status sap_apply_internal(dw_field f, double m0, const sap_params* sp, const 
   for (int cyc = 0; cyc < sp->ncycles; ++cyc)
     for (int colour = 0; colour < 2; ++colour)
       DW_TRY(launch_sap_colour(g, m0, prec, v, z, f->U[prec], colour, sp->nmr, cyc == 0 && colour == 0 ? 1 : 0, nrhs,
-                               n, n, stream));
+                               n, n, stream, nullptr, f->C[prec]));
   return DW_OK;
 }
 

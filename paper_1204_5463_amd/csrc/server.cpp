@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -113,6 +114,14 @@ void worker(dw_server s) {
     if (status == DW_OK) {
       dw_field f = nullptr;
       status = dw_field_create(s->ictx, rq->r.L, rq->r.block, rq->r.U, st, &f);
+      if (status == DW_OK && rq->r.csw != 0.0) {
+        status = dw_field_set_clover(f, rq->r.csw, st);
+        if (status != DW_OK) {
+          err = dw_last_error();
+          dw_field_destroy(f);
+          f = nullptr;
+        }
+      }
       if (status == DW_OK) {
         status = fgmresdr_solve(f, rq->r.m0, &rq->r.params, rq->r.b, rq->r.x, rq->r.nrhs, rq->stats.data(), st);
         if (status != DW_OK && status != DW_ENOTCONV) err = dw_last_error();
@@ -149,7 +158,7 @@ size_t dw_request_footprint(const dw_request* q) {
   if (!q || q->nrhs < 1 || !valid_geom(q, &g)) return 0;
   const int prec = q->params.sap.storage;
   if (prec < 0 || prec > 3 || q->params.m < 1 || q->params.m > 48) return 0;
-  const size_t links = (size_t)g.V * 36 * (16 + 8 + 4 + 4);
+  const size_t links = (size_t)g.V * 36 * (16 + 8 + 4 + 4) * (q->csw != 0.0 ? 2 : 1);  // + clover copies
   return links + solver_bytes(g.V, q->params.m, prec, q->params.flags, q->nrhs);
 }
 
@@ -201,7 +210,7 @@ dw_status dw_server_destroy(dw_server s) {
 
 dw_status solve_submit(dw_server s, const dw_request* q, uint64_t* ticket) {
   clear_error();
-  if (!s || !q || !ticket || !q->U || !q->b || !q->x || q->nrhs < 1) {
+  if (!s || !q || !ticket || !q->U || !q->b || !q->x || q->nrhs < 1 || !std::isfinite(q->csw)) {
     set_error("solve_submit: invalid argument");
     return DW_EINVAL;
   }

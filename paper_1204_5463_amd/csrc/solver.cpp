@@ -234,7 +234,8 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         for (int cy = 0; cy < P->sap.ncycles; ++cy)
           for (int colour = 0; colour < 2; ++colour)
             DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
-                                     cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, W.rlist.as<int>()));
+                                     cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, W.rlist.as<int>(),
+                                     f->C[prec]));
         if (zprec != DW_PREC_F64)
           for (int r : part)
             DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), DW_PREC_F64,
@@ -242,7 +243,7 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         // w = D z_j in FP64 on the stored z_j, all participants in one launch
         DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.Z.as<double>() + 2 * (long long)j * n, 1.0,
                                    f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, np, (long long)m * n, n, s,
-                                   W.rlist.as<int>()));
+                                   W.rlist.as<int>(), f->C[DW_PREC_F64]));
         // Gram-Schmidt with delayed reorthogonalisation, per RHS
         for (int r : part) {
           Rhs& q = R[r];
@@ -308,7 +309,7 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
     }
     DW_TRY(set_rlist(W, cyc, s));
     DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, W.x.p, 1.0, f->U[DW_PREC_F64], W.r.as<double>(), W.b.as<double>(),
-                               1, (int)cyc.size(), n, n, s, W.rlist.as<int>()));
+                               1, (int)cyc.size(), n, n, s, W.rlist.as<int>(), f->C[DW_PREC_F64]));
     // shared deflation space (multi-RHS): once RHS 0 has a deflation space,
     // every other RHS projects its restart residual onto it. The space
     // satisfies D Z_0 = V_0 H_0 (the k+1 leading columns of V_0, k of Z_0 and

@@ -19,6 +19,7 @@ struct Tuner {
   int L[4];
   const double* U;
   double m0;
+  double csw;
   const double* b;
   double* x;
   int nrhs;
@@ -45,6 +46,7 @@ struct Tuner {
       f = nullptr;
     }
     DW_TRY(dw_field_create(ctx, L, B, U, st, &f));
+    if (csw != 0.0) DW_TRY(dw_field_set_clover(f, csw, st));
     std::copy(B, B + 4, fblock);
     return DW_OK;
   }
@@ -127,7 +129,7 @@ std::vector<std::array<int, 4>> default_blocks(const int L[4]) {
 
 }  // namespace
 
-extern "C" dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U, double m0,
+extern "C" dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U, double m0, double csw,
                                  const fgmresdr_params* base, const dw_tune_space* space, const double* b, double* x,
                                  int32_t nrhs, dw_tune_trial* trials, int32_t max_trials, int32_t* ntrials,
                                  fgmresdr_params* best, hipStream_t stream) {
@@ -150,7 +152,11 @@ extern "C" dw_status dw_autotune(dw_ctx ctx, const int32_t L[4], const double* U
     set_error("dw_autotune: the base block shape is not valid for the lattice");
     return DW_EINVAL;
   }
-  Tuner T{ctx, {Li[0], Li[1], Li[2], Li[3]}, U, m0, b, x, nrhs, stream, space, trials, max_trials};
+  if (!std::isfinite(csw)) {
+    set_error("dw_autotune: non-finite csw");
+    return DW_EINVAL;
+  }
+  Tuner T{ctx, {Li[0], Li[1], Li[2], Li[3]}, U, m0, csw, b, x, nrhs, stream, space, trials, max_trials};
   dw_status s = DW_OK;
   auto step = [&](fgmresdr_params p) {
     if (s == DW_OK) s = T.run(p);

@@ -90,3 +90,13 @@ def test_dsw_gamma5_hermitian():
     # block operator keeps the (site-local) term
     yb = W.apply_D_blocks(U, m0, x, (2, 2, 2, 2), C) - W.apply_D_blocks(U, m0, x, (2, 2, 2, 2))
     assert np.max(np.abs(yb - Cl.apply_clover(C, x))) < 1e-14
+
+
+def test_site_by_site_matches_whole_lattice():
+    U = synth.gauge_field(L, 0.6, 6)
+    C = Cl.clover_term(U, 1.4)
+    V = int(np.prod(L))
+    sites = [0, 1, 17, V // 2, V - 1]
+    Cs = Cl.clover_at_sites(U, 1.4, sites)
+    flat = C.reshape((V, 4, 3, 4, 3))
+    assert np.max(np.abs(Cs - flat[sites])) < 1e-14
