@@ -343,6 +343,7 @@ def main():
     ap.add_argument("--skip-dslash", action="store_true", help="skip the per-precision operator timings")
     ap.add_argument("--skip-v32", action="store_true", help="skip the FP32-basis comparison solve")
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
+    ap.add_argument("--csw", type=float, default=0.0, help="clover coefficient (0: plain Wilson operator)")
     ap.add_argument("--params", default=None,
                     help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4,shared=1 (exploration)")
     ap.add_argument("--also-k0", action="store_true", help="also run FGMRES(m) (k = 0) on the same system")
@@ -419,12 +420,15 @@ def main():
         ts = time.perf_counter()
         # the workload fixes FGMRES-DR(m, k); the SAP parameters are tuned
         space = P.TuneSpace(nmr=(4, 12), s=(2, 8), passes=2, iter_cap=2.0)
-        params, trials = P.autotune(ctx, L, Ud, m0, params, bt, space=space, cache=P.TuneCache(args.autotune))
+        params, trials = P.autotune(ctx, L, Ud, m0, params, bt, space=space, cache=P.TuneCache(args.autotune),
+                                    csw=args.csw)
         for t in trials:
             log(f"[bench]   trial {t}")
         tune = {"trials": len(trials), "tuning_s": round(time.perf_counter() - ts, 1)}
         torch.cuda.empty_cache()
     f = P.Field(ctx, L, params.sap.block, Ud)
+    if args.csw:
+        f.set_clover(args.csw)
     del Ud
 
     def summary(st):
@@ -603,11 +607,12 @@ def main():
         "dtype": "f32+f64" if prec != P.DW_PREC_F64 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload} lattice, eps={wl['eps']} SU(3) links (seed 0), m0={m0:.6f} "
-                               f"near-critical, "
+                               + (f"clover c_sw={args.csw}, " if args.csw else "") + "near-critical, "
                                + (f"{nrhs} point-source+noise RHS in lock-step, " if wl.get("rhs") == "point"
                                   else f"{nrhs} Gaussian RHS, ")
                                + describe(params, P) + (" (autotuned)" if tune is not None else ""),
                    "lattice": list(L), "m0": m0, "m0_from": mass_src, "sap_storage": wl["storage"], "nrhs": nrhs,
+                   "csw": args.csw,
                    "parallelism": "single GPU"},
         "iterations": st0.iterations,
         "cycles": st0.cycles,
