@@ -50,6 +50,37 @@ __device__ __forceinline__ void clover_acc(const SC* __restrict__ Cb, int bvol, 
   }
 }
 
+// y += s * C x for one site, with x read through xin(comp) one chirality at
+// a time (fewer live registers than clover_acc).
+template <typename T, typename SC, typename XF>
+__device__ __forceinline__ void clover_acc_f(const SC* __restrict__ Cb, int bvol, int l, XF&& xin, T s,
+                                             cplx<T> y[12]) {
+#pragma unroll
+  for (int chi = 0; chi < 2; ++chi) {
+    const SC* c = Cb + (long long)chi * 18 * bvol + l;
+    cplx<T> v[6], w[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = xin(6 * chi + i);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const cplx<T> d = ld<T>(c + q * bvol);
+      w[2 * q] = d.re * v[2 * q];
+      w[2 * q + 1] = d.im * v[2 * q + 1];
+    }
+    int q = 3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 6; ++j) {
+        const cplx<T> o = ld<T>(c + (q++) * bvol);
+        w[i] += o * v[j];
+        w[j] += cdot(o, v[i]);
+      }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[6 * chi + i] += s * w[i];
+  }
+}
+
 // flops of clover_acc per site: 2 x (6 x 2 + 15 x 2 x 8)
 constexpr double kCloverFlops = 504.0;
 

@@ -142,15 +142,8 @@ __global__ void __launch_bounds__(MAXT)
           [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); }, u_halo, acc);
       if constexpr (CLOV) {
         // -1/2 hops + C z = -1/2 (hops - 2 C z)
-        cplx<T> zo[12], cz[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          zo[c] = rho_s[c * bvol + l];
-          cz[c] = mk<T>(0, 0);
-        }
-        clover_acc<T>(Cl + (long long)b * kCloverPairs * bvol, bvol, l, zo, cz);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] -= (T)2 * cz[c];
+        clover_acc_f<T>(Cl + (long long)b * kCloverPairs * bvol, bvol, l,
+                        [&](int c) { return rho_s[c * bvol + l]; }, (T)-2, acc);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c)
@@ -185,15 +178,8 @@ __global__ void __launch_bounds__(MAXT)
         // (hoisted, they would hold 72 registers)
         int cofs = 0;
         asm volatile("" : "+v"(cofs));
-        cplx<T> ro[12], cr[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          ro[c] = rho_s[c * bvol + l];
-          cr[c] = mk<T>(0, 0);
-        }
-        clover_acc<T>(Cl + (long long)b * kCloverPairs * bvol + cofs, bvol, l, ro, cr);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) p[c] -= (T)2 * cr[c];
+        clover_acc_f<T>(Cl + (long long)b * kCloverPairs * bvol + cofs, bvol, l,
+                        [&](int c) { return rho_s[c * bvol + l]; }, (T)-2, p);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
