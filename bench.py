@@ -320,6 +320,7 @@ def serve(args):
                                f"{args.slots} slots" + (", captured steps" if args.serve_graphs else ""),
                    "m_c_from": {n: mc[n][1] for n in names}},
         "makespan_s": round(makespan, 3),
+        "offered_requests_per_s": round(len(reqs) / reqs[-1]["arrival"], 4),
         "rhs_solves_per_s": round(rhs_total / makespan, 4),
         "p50_latency_ms": round(1e3 * pct(lat, 0.5), 1),
         "p99_latency_ms": round(1e3 * pct(lat, 0.99), 1),
@@ -342,6 +343,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--skip-dslash", action="store_true", help="skip the per-precision operator timings")
     ap.add_argument("--skip-v32", action="store_true", help="skip the FP32-basis comparison solve")
+    ap.add_argument("--all-precisions", action="store_true",
+                    help="also time the solve with FP16, BF16, FP32 and FP64 SAP storage")
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
     ap.add_argument("--csw", type=float, default=0.0, help="clover coefficient (0: plain Wilson operator)")
     ap.add_argument("--params", default=None,
@@ -539,6 +542,26 @@ def main():
         out_extra["fp32_basis"] = {"solves_per_s": round(nrhs / t32, 4),
                                    "iterations": max(s.iterations for s in s32),
                                    "true_relres": max(s.true_relres for s in s32)}
+    # ---- the same solve with each SAP storage precision
+    if args.all_precisions:
+        sp = {}
+        for name in ("f16", "bf16", "f32", "f64"):
+            pp = P.SolverParams(m=params.m, k=params.k, tol=params.tol, restart_t=params.restart_t,
+                                max_iter=params.max_iter, flags=params.flags,
+                                sap=P.SapParams(block=params.sap.block, ncycles=params.sap.ncycles,
+                                                nmr=params.sap.nmr, storage=P.PREC_NAMES[name]))
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            f.solve(m0, pp, bt)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            _, sx = f.solve(m0, pp, bt)
+            torch.cuda.synchronize()
+            tx = time.perf_counter() - ts
+            log(f"[bench] SAP {name}: {summary(sx)}, {tx:.3f} s")
+            sp[name] = {"solves_per_s": round(nrhs / tx, 4), "iterations": max(s.iterations for s in sx),
+                        "true_relres": max(s.true_relres for s in sx)}
+        out_extra["sap_precisions"] = sp
     # ---- FGMRES(m): the same solve without deflation
     if args.also_k0:
         pk0 = P.SolverParams(m=params.m, k=0, tol=params.tol, restart_t=params.restart_t,
