@@ -1,5 +1,6 @@
 """Writes tests/golden/critical_mass.json: the leftmost eigenvalues of the
-massless Wilson-Dirac operator D(0) for the seeded synthetic gauge fields,
+massless Wilson-Dirac operator D(0) (with the clover term where a
+coefficient is given) for the seeded synthetic gauge fields,
 from which the near-critical masses of the workloads are set.
 
 Uses only the FP64 oracle's operator (and SciPy's ARPACK). Since
@@ -22,11 +23,12 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
+from oracle import clover as Cl  # noqa: E402
 from oracle import wilson as W  # noqa: E402
 
 OUT = os.path.join(HERE, "critical_mass.json")
 
-# name: (L, eps, gauge seed)
+# name: (L, eps, gauge seed[, clover coefficient])
 FIELDS = {
     "8^4_eps0.3": ((8, 8, 8, 8), 0.3, 0),
     "8^4_eps0.7": ((8, 8, 8, 8), 0.7, 0),
@@ -35,18 +37,21 @@ FIELDS = {
     "12^4_eps0.6": ((12, 12, 12, 12), 0.6, 0),
     "16^3x32_eps0.6": ((16, 16, 16, 32), 0.6, 0),
     "16^3x32_eps0.7": ((16, 16, 16, 32), 0.7, 0),
+    "8^4_eps0.7_csw1.9": ((8, 8, 8, 8), 0.7, 0, 1.9),
+    "12^4_eps0.7_csw1.9": ((12, 12, 12, 12), 0.7, 0, 1.9),
 }
 
 
-def leftmost(L, eps, seed, nev=12, ncv=64, tol=1e-9):
+def leftmost(L, eps, seed, csw=0.0, nev=12, ncv=64, tol=1e-9):
     U = synth.gauge_field(L, eps, seed)
+    C = Cl.clover_term(U, csw) if csw else None
     shp = synth.lattice_shape(L) + (4, 3)
     n = int(np.prod(shp))
     count = [0]
 
     def mv(v):
         count[0] += 1
-        return W.apply_D(U, 0.0, v.reshape(shp).astype(np.complex128)).reshape(-1)
+        return W.apply_D(U, 0.0, v.reshape(shp).astype(np.complex128), C).reshape(-1)
 
     op = sla.LinearOperator((n, n), matvec=mv, dtype=np.complex128)
     v0 = synth.gaussian_spinor(L, 4242).reshape(-1)
@@ -58,15 +63,17 @@ def leftmost(L, eps, seed, nev=12, ncv=64, tol=1e-9):
 
 def main(names):
     for name in names:
-        L, eps, seed = FIELDS[name]
-        ev, nmv, secs = leftmost(L, eps, seed)
+        L, eps, seed = FIELDS[name][:3]
+        csw = FIELDS[name][3] if len(FIELDS[name]) > 3 else 0.0
+        ev, nmv, secs = leftmost(L, eps, seed, csw)
         data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         data[name] = {
-            "L": list(L), "eps": eps, "seed": seed,
+            "L": list(L), "eps": eps, "seed": seed, "csw": csw,
             "leftmost_eigenvalues_D0": [[float(e.real), float(e.imag)] for e in ev],
             "m_c": float(-ev[0].real),
             "matvecs": nmv, "seconds": round(secs, 1),
-            "method": "scipy.sparse.linalg.eigs(which='SR', k=12, ncv=64, tol=1e-9) on oracle.wilson.apply_D(U, 0, .)",
+            "method": "scipy.sparse.linalg.eigs(which='SR', k=12, ncv=64, tol=1e-9) on oracle.wilson.apply_D(U, 0, ., C) "
+                      "(C = oracle.clover.clover_term(U, csw) when csw != 0)",
         }
         json.dump(data, open(OUT, "w"), indent=1)
         print(name, "m_c", -ev[0].real, "edge", ev[:4], nmv, "matvecs", round(secs), "s", flush=True)
