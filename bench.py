@@ -128,7 +128,8 @@ def time_dslash(P, torch, f, m0, prec, reps=50, warm=10):
     e1.record(s)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    nbytes = V * 60 * P.PAIR_BYTES[prec]
+    # x read, 4 links read, y written (+ the clover term's 36 pairs)
+    nbytes = V * (60 + (36 if getattr(f, "csw", 0.0) else 0)) * P.PAIR_BYTES[prec]
     del xi, yi
     return ms, nbytes / ms / 1e6
 
