@@ -16,6 +16,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -339,6 +340,69 @@ def serve(args):
     print(json.dumps(line), flush=True)
 
 
+def sap_study(args):
+    """SAP iterated on its own, x_{k+1} = x_k + M (b - D x_k) with one SAP
+    cycle per iteration (Section 3, Fig. 5), on the workload's lattice and
+    block solves, at masses from well above to just below the critical one;
+    once with the workload's fixed MR step count and once with the adaptive
+    0.1 block-residual reduction (capped at twice that count). Prints one
+    JSON line with the residual histories and asymptotic rates."""
+    import numpy as np
+    import torch
+
+    import paper_1204_5463_amd as P
+    import synth
+
+    wl = WORKLOADS[args.workload]
+    L = wl["L"]
+    names, _ = wl["mass"]
+    m_c, src = mass_for((names, 0.0)) if names is not None else (None, None)
+    if m_c is None:
+        raise SystemExit("the study needs a workload with a known critical mass")
+    csw = args.csw or wl.get("csw", 0.0)
+    log(f"[study] {args.workload}: L={L} eps={wl['eps']} m_c={m_c:.6f} ({src}); generating inputs")
+    U = synth.gauge_field(L, wl["eps"], wl["seed"])
+    b = synth.gaussian_spinor(L, 1000)
+    ctx = P.Context(0)
+    f = P.Field(ctx, L, wl["block"], P.to_device(U))
+    del U
+    if csw:
+        f.set_clover(csw)
+    bt = P.to_device(b)
+    prec = P.PREC_NAMES[wl["storage"]]
+    deltas = [0.5, 0.2, 0.1, 0.05, 0.02, 0.01, 0.0, -0.02]
+    variants = {"fixed": P.SapParams(block=wl["block"], ncycles=1, nmr=wl["nmr"], storage=prec),
+                "adaptive": P.SapParams(block=wl["block"], ncycles=1, nmr=2 * wl["nmr"], storage=prec,
+                                        mr_reduction=0.1)}
+    out = {}
+    for vname, sp in variants.items():
+        rows = []
+        for d in deltas:
+            m0 = m_c + d
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, hist = f.sap_solve(m0, sp, bt, args.study_iters)
+            sec = time.perf_counter() - t0
+            n = len(hist) - 1
+            # asymptotic rate: the last 20 iterations before the residual
+            # reaches the FP64 floor
+            e = next((k for k, h in enumerate(hist) if h < 1e-12), n)
+            j = min(20, e)
+            rate = (hist[e] / hist[e - j]) ** (1.0 / j) if j > 0 and hist[e - j] > 0 else None
+            rows.append({"delta_m": d, "m0": round(m0, 6), "final_relres": hist[n], "rate": rate,
+                         "converges": bool(rate is not None and rate < 1.0),
+                         "ms_per_iteration": 1e3 * sec / max(n, 1),
+                         "history": [float(f"{h:.4g}") for h in hist]})
+            log(f"[study] {vname:8s} m0 = m_c {d:+.3f}: relres {hist[n]:.3e} after {n} iterations, "
+                f"rate {rate:.4f}, {1e3 * sec / max(n, 1):.2f} ms/iteration")
+        out[vname] = rows
+    print(json.dumps({"metric": "sap_standalone_study", "workload": args.workload, "lattice": list(L),
+                      "eps": wl["eps"], "csw": csw, "m_c": m_c, "m_c_source": src, "block": list(wl["block"]),
+                      "nmr": wl["nmr"], "storage": wl["storage"], "cycles_per_iteration": 1,
+                      "adaptive_reduction": 0.1, "iterations": args.study_iters, "data": "synthetic",
+                      "variants": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +418,8 @@ def main():
     ap.add_argument("--m0", type=float, default=None, help="override the workload's mass (exploration only)")
     ap.add_argument("--csw", type=float, default=0.0, help="clover coefficient (0: plain Wilson operator)")
     ap.add_argument("--params", default=None,
-                    help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4,shared=1 (exploration)")
+                    help="override solver parameters, e.g. s=3,nmr=7,m=30,k=6,block=4x4x4x4,shared=1,red=0.1 "
+                         "(exploration)")
     ap.add_argument("--also-k0", action="store_true", help="also run FGMRES(m) (k = 0) on the same system")
     ap.add_argument("--sequential", action="store_true",
                     help="multi-RHS workloads: also time the RHS one after another")
@@ -367,6 +432,10 @@ def main():
     ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--serve-graphs", action="store_true",
                     help="serving: replay captured Arnoldi steps (HIP graphs) in single-RHS requests")
+    ap.add_argument("--sap-study", action="store_true",
+                    help="SAP as a stand-alone solver at masses around the critical one, fixed and adaptive "
+                         "MR block solves, instead of the solve benchmark")
+    ap.add_argument("--study-iters", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -374,6 +443,8 @@ def main():
         sys.exit(2)
     if args.serve:
         return serve(args)
+    if args.sap_study:
+        return sap_study(args)
 
     import numpy as np
     import torch
@@ -421,6 +492,8 @@ def main():
                 params.flags = (params.flags & ~P.SOLVE_GRAPHS) | (P.SOLVE_GRAPHS if int(val) else 0)
             elif key == "v32":
                 params.flags = (params.flags & ~P.SOLVE_V32) | (P.SOLVE_V32 if int(val) else 0)
+            elif key == "red":
+                params.sap.mr_reduction = float(val)
             else:
                 raise SystemExit(f"unknown parameter {key}")
     tune = None
@@ -518,8 +591,7 @@ def main():
     if not args.skip_fp64:
         p64 = P.SolverParams(m=params.m, k=params.k, tol=params.tol, restart_t=params.restart_t,
                              max_iter=params.max_iter, flags=params.flags,
-                             sap=P.SapParams(block=params.sap.block, ncycles=params.sap.ncycles, nmr=params.sap.nmr,
-                                             storage=P.DW_PREC_F64))
+                             sap=dataclasses.replace(params.sap, storage=P.DW_PREC_F64))
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         ts = time.perf_counter()
@@ -555,8 +627,7 @@ def main():
         for name in ("f16", "bf16", "f32", "f64"):
             pp = P.SolverParams(m=params.m, k=params.k, tol=params.tol, restart_t=params.restart_t,
                                 max_iter=params.max_iter, flags=params.flags,
-                                sap=P.SapParams(block=params.sap.block, ncycles=params.sap.ncycles,
-                                                nmr=params.sap.nmr, storage=P.PREC_NAMES[name]))
+                                sap=dataclasses.replace(params.sap, storage=P.PREC_NAMES[name]))
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
             f.solve(m0, pp, bt)

@@ -76,14 +76,20 @@ typedef struct dw_server_s* dw_server;
  *             domains per direction (Section 2, red/black colouring); they
  *             must equal the block extents the field was created with.
  *   ncycles   SAP cycles s per application (one cycle = both colours).
- *   nmr       minimal-residual steps per block solve, from y = 0.
- *   storage   dw_prec of the preconditioner's fields. */
+ *   nmr       minimal-residual steps per block solve, from y = 0 (with
+ *             mr_reduction > 0: the largest number of steps).
+ *   storage   dw_prec of the preconditioner's fields.
+ *   mr_reduction  0: every block takes nmr steps (Section 5). In (0, 1): an
+ *             inexact block solve that stops, block by block, at the first
+ *             step whose residual satisfies ||rho|| <= mr_reduction ||r||
+ *             (Section 3); r is the block's right-hand side. */
 typedef struct sap_params {
   int32_t block[4];
   int32_t ncycles;
   int32_t nmr;
   int32_t storage;
   int32_t reserved;
+  double mr_reduction;
 } sap_params;
 
 /* FGMRES-DR parameters (Alg. 4; Section 4.7).
@@ -191,6 +197,23 @@ dw_status dw_unpack(dw_field field, int32_t prec, const void* x_int, double* x, 
  * z^l += y^l. v and z: canonical spinor arrays (nrhs each), no overlap. */
 dw_status sap_precondition(dw_field field, double m0, const sap_params* sap, const double* v, double* z,
                            int32_t nrhs, hipStream_t stream);
+
+/* SAP as a stand-alone solver for D x = b (Alg. 2 iterated; Section 3 on
+ * its divergence as the mass approaches the critical one; Fig. 5):
+ *   x_0 = 0,  x_{k+1} = x_k + M (b - D x_k),
+ * M being `sap.ncycles` SAP cycles as in sap_precondition. Since a SAP cycle
+ * started from z = 0 on the residual continues the sweep on x, x_k equals
+ * k * ncycles cycles of Alg. 2 applied to D x = b. The residual b - D x_k
+ * and x are FP64 (the preconditioner runs at `sap.storage`, its input
+ * scaled per iteration to unit RMS), so low-precision storage does not
+ * limit the attainable residual.
+ * b, x: canonical spinor arrays (one right-hand side) on the device, no
+ * overlap; x receives x_niter. resid: host array of niter + 1 doubles,
+ * resid[k] = ||b - D x_k|| / ||b|| (FP64). The call returns when done.
+ * An exact solution (zero residual) ends the iteration early, the remaining
+ * entries of resid set to 0. DW_EINVAL: niter < 0, b = 0, bad sap_params. */
+dw_status sap_solve(dw_field field, double m0, const sap_params* sap, const double* b, double* x, int32_t niter,
+                    double* resid, hipStream_t stream);
 
 /* Solves D x = b by SAP-preconditioned FGMRES-DR(m, k) (Alg. 4) from x = 0
  * for nrhs right-hand sides (solved in lock-step, every SAP and stencil

@@ -7,7 +7,10 @@ Follows the paper:
   * Alg. 2 (Section 2): SAP, all blocks of one colour, then the other;
   * Section 3: inexact block solves by a fixed number of minimal-residual
     (MR) steps, independent of the accuracy reached (as in the experiments
-    of Section 5);
+    of Section 5), or, adaptively, until the block residual has dropped by
+    a given factor (the factor 10 of Section 3), block by block;
+  * Section 3 and Fig. 5: SAP iterated on its own as a solver, which
+    converges for heavy masses and diverges near the critical one;
   * Section 4: with exact block solves, s SAP cycles from a zero start give
     the truncated series M_s = sum_{j<s} (A_L^{-1} A_U)^j A_L^{-1} of the
     block splitting D = A_L - A_U (the printed formula lacks the power j;
@@ -20,6 +23,11 @@ Readings of the paper taken here:
     (it contains the block at the origin) and is processed first;
   * MR starts from y = 0, uses alpha = (p^H rho)/(p^H p) over the block's
     sites (alpha = 0 if p = 0) and no relaxation;
+  * the adaptive inexact solve tests ||rho_n|| <= delta ||r^l|| before each
+    step n = 0, 1, ..., stops the block at the first n that passes, and
+    never takes more than n_MR steps;
+  * the stand-alone SAP solver starts from x = 0 and each iteration applies
+    s cycles to the current residual: x_{k+1} = x_k + M_s (b - D x_k);
   * one SAP cycle = both colours once.
 
 ``C`` (optional) is a site-local 12x12 term added to the operator, the
@@ -78,31 +86,43 @@ def block_broadcast(s, L, block):
     return e
 
 
-def mr_blocks(U, m0, L, block, r, nmr, C=None):
+def block_norm(a, L, block):
+    """Euclidean norm of a spinor field over each block: (Nt, Nz, Ny, Nx)."""
+    return np.sqrt(block_sum(np.abs(a) ** 2, L, block))
+
+
+def mr_blocks(U, m0, L, block, r, nmr, C=None, reduction=0.0):
     """n_MR minimal-residual steps for D^l y^l = r^l on every block at once.
 
     ``r`` must vanish outside the blocks being solved (the hop cut of D^l
     keeps blocks independent). Returns (y, rho) with rho = r - D^l y.
+    ``reduction`` = delta > 0: a block stops before the first step n at
+    which ||rho_n|| <= delta ||r^l|| (Section 3); n_MR is then the cap.
     """
     y = np.zeros_like(r)
     rho = r.copy()
+    r_norm = block_norm(r, L, block)
+    running = np.ones(r_norm.shape, dtype=bool)
     for _ in range(nmr):
+        if reduction > 0.0:
+            running &= ~(block_norm(rho, L, block) <= reduction * r_norm)
         p = apply_D_blocks(U, m0, rho, block, C)
         num = block_sum(np.conj(p) * rho, L, block)           # p^H rho per block
         den = block_sum(np.abs(p) ** 2, L, block).real          # p^H p per block
         alpha = np.where(den > 0.0, num / np.where(den > 0.0, den, 1.0), 0.0)
+        alpha = np.where(running, alpha, 0.0)                   # stopped blocks keep y
         a = block_broadcast(alpha, L, block)[..., None, None]
         y = y + a * rho
         rho = rho - a * p
     return y, rho
 
 
-def sap(U, m0, L, block, ncycles, nmr, v, block_solver=None, C=None):
+def sap(U, m0, L, block, ncycles, nmr, v, block_solver=None, C=None, reduction=0.0):
     """z = M v: ``ncycles`` SAP cycles (Alg. 2) from z = 0.
 
     Per cycle and colour: r = (v - D z) on the blocks of that colour, block
-    solves D^l y^l = r^l (n_MR MR steps, or ``block_solver`` if given), then
-    z += y on those blocks.
+    solves D^l y^l = r^l (n_MR MR steps, adaptive with ``reduction`` > 0, or
+    ``block_solver`` if given), then z += y on those blocks.
     """
     check_blocking(L, block)
     z = np.zeros_like(v)
@@ -111,11 +131,28 @@ def sap(U, m0, L, block, ncycles, nmr, v, block_solver=None, C=None):
         for c in (0, 1):
             r = (v - apply_D(U, m0, z, C)) * masks[c]
             if block_solver is None:
-                y, _ = mr_blocks(U, m0, L, block, r, nmr, C)
+                y, _ = mr_blocks(U, m0, L, block, r, nmr, C, reduction)
             else:
                 y = block_solver(r, c) * masks[c]
             z = z + y
     return z
+
+
+def sap_solve(U, m0, L, block, ncycles, nmr, b, niter, C=None, reduction=0.0, block_solver=None):
+    """SAP as a stand-alone solver (Section 3, Fig. 5): x_0 = 0,
+    x_{k+1} = x_k + M_s (b - D x_k) with M_s = ``ncycles`` SAP cycles.
+
+    Returns (x_niter, [||b - D x_k|| / ||b|| for k = 0..niter]).
+    """
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    hist = []
+    for k in range(niter + 1):
+        r = b - apply_D(U, m0, x, C)
+        hist.append(np.linalg.norm(r) / bnorm)
+        if k < niter:
+            x = x + sap(U, m0, L, block, ncycles, nmr, r, block_solver, C, reduction)
+    return x, hist
 
 
 def block_list(L, block):

@@ -49,7 +49,7 @@ class NotConverged(DwError):
 
 class _SapParams(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32 * 4), ("ncycles", ctypes.c_int32), ("nmr", ctypes.c_int32),
-                ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mr_reduction", ctypes.c_double)]
 
 
 class _SolverParams(ctypes.Structure):
@@ -113,17 +113,23 @@ class _Allocator(ctypes.Structure):
 
 @dataclasses.dataclass
 class SapParams:
-    """SAP preconditioner (Alg. 2): block extents, cycles s, MR steps, storage precision."""
+    """SAP preconditioner (Alg. 2): block extents, cycles s, MR steps, storage precision.
+
+    mr_reduction > 0 makes the block solves inexact in the adaptive sense of
+    Section 3: each block stops at the first MR step whose residual is at most
+    mr_reduction times its right-hand side's norm (nmr bounds the steps)."""
     block: tuple = (4, 4, 4, 4)
     ncycles: int = 1
     nmr: int = 4
     storage: int = DW_PREC_F64
+    mr_reduction: float = 0.0
 
     def _c(self):
         p = _SapParams()
         for i in range(4):
             p.block[i] = int(self.block[i])
         p.ncycles, p.nmr, p.storage, p.reserved = int(self.ncycles), int(self.nmr), int(self.storage), 0
+        p.mr_reduction = float(self.mr_reduction)
         return p
 
 
@@ -185,6 +191,7 @@ def load(path: str = LIB_PATH):
         "dw_pack": (st, [vp, i32, vp, vp, i32, vp]),
         "dw_unpack": (st, [vp, i32, vp, vp, i32, vp]),
         "sap_precondition": (st, [vp, dbl, ctypes.POINTER(_SapParams), vp, vp, i32, vp]),
+        "sap_solve": (st, [vp, dbl, ctypes.POINTER(_SapParams), vp, vp, i32, ctypes.POINTER(dbl), vp]),
         "fgmresdr_solve": (st, [vp, dbl, ctypes.POINTER(_SolverParams), vp, vp, i32, ctypes.POINTER(_Stats), vp]),
         "dw_profile_enable": (st, [vp, i32]),
         "dw_profile_get": (st, [vp, i32, ctypes.POINTER(_KStats)]),
@@ -371,6 +378,20 @@ class Field:
                                       self._nrhs(v), _stream(stream)), "sap_precondition")
         return z
 
+    def sap_solve(self, m0: float, params: SapParams, b: torch.Tensor, niter: int, x: torch.Tensor | None = None,
+                  stream=None):
+        """SAP as a stand-alone solver: x_{k+1} = x_k + M (b - D x_k) from x_0 = 0.
+        Returns (x_niter, relative FP64 residuals for k = 0..niter). Synchronous."""
+        if x is None:
+            x = torch.empty_like(b)
+        if self._nrhs(b) != 1:
+            raise ValueError("sap_solve takes one right-hand side")
+        p = params._c()
+        res = (ctypes.c_double * (int(niter) + 1))()
+        _check(lib().sap_solve(self.handle, float(m0), ctypes.byref(p), _dev_ptr(b), _dev_ptr(x), int(niter), res,
+                               _stream(stream)), "sap_solve")
+        return x, list(res)
+
     def solve(self, m0: float, params: SolverParams, b: torch.Tensor, x: torch.Tensor | None = None,
               stream=None, raise_on_notconv=True):
         """x = D^{-1} b by SAP-preconditioned FGMRES-DR (Alg. 4). Returns (x, [SolveStats])."""
@@ -508,7 +529,8 @@ class TuneSpace:
 def _params_from_c(p: _SolverParams) -> SolverParams:
     return SolverParams(m=p.m, k=p.k, max_iter=p.max_iter, tol=p.tol, restart_t=p.restart_t,
                         sap=SapParams(block=tuple(p.sap.block), ncycles=p.sap.ncycles, nmr=p.sap.nmr,
-                                      storage=p.sap.storage), shared_defl=p.shared_defl, flags=p.flags)
+                                      storage=p.sap.storage, mr_reduction=p.sap.mr_reduction),
+                        shared_defl=p.shared_defl, flags=p.flags)
 
 
 class TuneCache:
@@ -537,14 +559,15 @@ class TuneCache:
         p = e["params"]
         return SolverParams(m=p["m"], k=p["k"], max_iter=p["max_iter"], tol=p["tol"], restart_t=p["restart_t"],
                             sap=SapParams(block=tuple(p["block"]), ncycles=p["ncycles"], nmr=p["nmr"],
-                                          storage=p["storage"]))
+                                          storage=p["storage"], mr_reduction=p.get("mr_reduction", 0.0)))
 
     def put(self, key, params: SolverParams, trials=()):
         import json
         d = self._load()
         d[key] = {"params": {"m": params.m, "k": params.k, "max_iter": params.max_iter, "tol": params.tol,
                              "restart_t": params.restart_t, "block": list(params.sap.block),
-                             "ncycles": params.sap.ncycles, "nmr": params.sap.nmr, "storage": params.sap.storage},
+                             "ncycles": params.sap.ncycles, "nmr": params.sap.nmr, "storage": params.sap.storage,
+                             "mr_reduction": params.sap.mr_reduction},
                   "trials": [dict(t) for t in trials]}
         tmp = self.path + ".tmp"
         with open(tmp, "w") as fh:

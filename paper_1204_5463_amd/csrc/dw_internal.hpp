@@ -165,6 +165,7 @@ dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, 
 // z at FP64 (prec F64) or FP32 (otherwise). z_zero: z is zero on entry.
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
                             int nmr, int z_zero, int nrhs, long long v_rhs_stride, long long z_rhs_stride,
-                            hipStream_t s, const int* rlist = nullptr, const void* C = nullptr);
+                            hipStream_t s, const int* rlist = nullptr, const void* C = nullptr,
+                            double mr_reduction = 0.0);
 
 }  // namespace dw

@@ -11,6 +11,13 @@
 //      they fit (FP32/FP16/BF16 storage), the block's links staged in LDS
 //      once so the MR steps touch no global memory;
 //   3. z += y on the block.
+// With red2 = delta^2 > 0 the block solve is inexact in the adaptive sense
+// (Section 3): a block stops at the first step n whose residual satisfies
+// ||rho_n||^2 <= delta^2 ||r||^2, nmr being the largest step count. Only
+// ||r||^2 takes a reduction of its own; each MR step lowers the squared
+// residual norm by |p^H rho|^2 / p^H p (rho - alpha p is orthogonal to p),
+// which the step's reductions already give, so the MR loop keeps its
+// per-site work and the whole workgroup stops together.
 // With z_zero set (first colour of the first cycle) z is not read and is
 // initialised here: y on this colour's blocks, zero on the other colour's.
 // Same-colour blocks never read each other's z, so updating z in place is
@@ -63,10 +70,10 @@ template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL
 __global__ void __launch_bounds__(MAXT)
     k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
                  int nmr, int z_zero, long long vs, long long zs, int nr, const int* __restrict__ rlist,
-                 const SG* __restrict__ Cl) {
+                 const SG* __restrict__ Cl, T red2) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int bvol = BS > 0 ? BS * BS * BS * BS : g.bvol;
-  // LDS: [links 36 x bvol (LDSL)] [rho 12 x bvol] [reduction 2 x nw x 3]
+  // LDS: [links 36 x bvol (LDSL)] [rho 12 x bvol] [rho16 (P16)] [reduction 2 x nw x 3] [||r||^2 nw]
   SG* lks = reinterpret_cast<SG*>(smem);
   const size_t lbytes = LDSL ? (((size_t)36 * bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
   cplx<T>* rho_s = reinterpret_cast<cplx<T>*>(smem + lbytes);
@@ -159,7 +166,24 @@ __global__ void __launch_bounds__(MAXT)
     for (int c = 0; c < 12; ++c) put_rho(c, l, ld<T>(vb + c * bvol + l));
   }
 
+  // adaptive stop: rr0 = ||r||^2 over the block, rr = ||rho_it||^2
+  const bool adapt = red2 > (T)0;
+  T rr0 = 0, rr = 0;
+  if (adapt) {
+    __syncthreads();  // rho written
+    T sq = 0;
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sq += norm2(rho_s[c * bvol + l]);
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) red[6 * nw + wave] = sq;
+    __syncthreads();
+    for (int w = 0; w < nw; ++w) rr0 += red[6 * nw + w];
+    rr = rr0;
+  }
   for (int it = 0; it < nmr; ++it) {
+    if (adapt && rr <= red2 * rr0) break;  // uniform over the workgroup
     __syncthreads();  // rho (and staged links) visible to the whole block
     cplx<T> p[12];
     T nre = 0, nim = 0, den = 0;
@@ -208,6 +232,7 @@ __global__ void __launch_bounds__(MAXT)
       den += rb[w * 3 + 2];
     }
     const cplx<T> alpha = den > (T)0 ? mk<T>(nre / den, nim / den) : mk<T>(0, 0);
+    if (adapt && den > (T)0) rr -= (nre * nre + nim * nim) / den;
     if (active) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -235,12 +260,12 @@ __global__ void __launch_bounds__(MAXT)
 
 template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS, bool CLOV>
 dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C, double red2) {
   const int threads = ((g.bvol + kWave - 1) / kWave) * kWave;
   const size_t lbytes = LDSL ? (((size_t)36 * g.bvol * sizeof(SG) + 15) & ~(size_t)15) : 0;
   constexpr bool P16 = std::is_same<SG, s16>::value && std::is_same<T, float>::value;
   const size_t shmem = lbytes + (size_t)12 * g.bvol * sizeof(cplx<T>) + (P16 ? (size_t)12 * g.bvol * 4 : 0) +
-                       (size_t)2 * 3 * (threads / kWave) * sizeof(T);
+                       (size_t)(2 * 3 + 1) * (threads / kWave) * sizeof(T);
   if (shmem > 160 * 1024) {
     set_error("SAP block of %d sites needs %zu bytes of LDS", g.bvol, shmem);
     return DW_EINVAL;
@@ -257,11 +282,12 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
   KTimer kt(DW_K_SAP, s);
   hipLaunchKernelGGL((k_sap_colour<T, SV, SZ, SG, MAXT, LDSL, BS, CLOV>), grid, threads, shmem, s, g, colour,
                      (T)(4.0 + m0), (const SV*)v, (SZ*)z, (const SG*)U, nmr, z_zero, vs, zs, nrhs, rlist,
-                     (const SG*)C);
+                     (const SG*)C, (T)red2);
   DW_CHECK_LAUNCH();
   // algorithmic traffic per site of this colour: v, 4 links, z read (or the
   // other colour's z cleared) and z written; flops: block residual stencil
-  // plus nmr MR steps (block stencil over the kept hops + 4 block vector ops)
+  // plus nmr MR steps (block stencil over the kept hops + 4 block vector ops);
+  // with the adaptive stop nmr is only the cap and the flops an upper bound
   double kept = 0;
   for (int mu = 0; mu < 4; ++mu) kept += 2.0 * (g.B[mu] - 1) / g.B[mu];
   const double sites = (double)g.nbc * g.bvol * nrhs;
@@ -274,7 +300,8 @@ dw_status launch_t(const Geom& g, double m0, const void* v, void* z, const void*
 
 template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool CLOV>
 dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C,
+                   double red2) {
   // Stage the block's links in LDS only when that keeps several workgroups
   // per CU: the MR steps are VALU bound and lose more to lower occupancy
   // than they gain from fewer cached link reads (measured on 4^4 blocks
@@ -284,46 +311,49 @@ dw_status launch_m(const Geom& g, double m0, const void* v, void* z, const void*
   if constexpr (MAXT == 256)
     if (hyper4 && need > 40 * 1024)
       return launch_t<T, SV, SZ, SG, 256, false, 4, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s,
-                                                          C);
+                                                          C, red2);
   if (need <= 40 * 1024)
     return launch_t<T, SV, SZ, SG, MAXT, true, 0, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s,
-                                                        C);
+                                                        C, red2);
   return launch_t<T, SV, SZ, SG, MAXT, false, 0, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s,
-                                                       C);
+                                                       C, red2);
 }
 
 template <typename T, typename SV, typename SZ, typename SG, bool CLOV>
 dw_status launch_b(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
+                   int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C,
+                   double red2) {
   if (g.bvol <= 256)
-    return launch_m<T, SV, SZ, SG, 256, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+    return launch_m<T, SV, SZ, SG, 256, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
   if (g.bvol <= 512)
-    return launch_m<T, SV, SZ, SG, 512, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
-  return launch_m<T, SV, SZ, SG, 1024, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+    return launch_m<T, SV, SZ, SG, 512, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
+  return launch_m<T, SV, SZ, SG, 1024, CLOV>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
 }
 
 template <typename T, typename SV, typename SZ, typename SG>
 dw_status launch(const Geom& g, double m0, const void* v, void* z, const void* U, int colour, int nmr, int z_zero,
-                 int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C) {
-  if (C) return launch_b<T, SV, SZ, SG, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
-  return launch_b<T, SV, SZ, SG, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+                 int nrhs, long long vs, long long zs, const int* rlist, hipStream_t s, const void* C,
+                   double red2) {
+  if (C) return launch_b<T, SV, SZ, SG, true>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
+  return launch_b<T, SV, SZ, SG, false>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
 }
 
 }  // namespace
 
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
                             int nmr, int z_zero, int nrhs, long long vs, long long zs, hipStream_t s,
-                            const int* rlist, const void* C) {
+                            const int* rlist, const void* C, double mr_reduction) {
   if (nrhs < 1) return DW_OK;
+  const double red2 = mr_reduction * mr_reduction;
   switch (prec) {
     case DW_PREC_F64:
-      return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+      return launch<double, s64, s64, s64>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
     case DW_PREC_F32:
-      return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+      return launch<float, s32, s32, s32>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
     case DW_PREC_F16:
-      return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+      return launch<float, s16, s32, s16>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
     case DW_PREC_BF16:
-      return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C);
+      return launch<float, sbf, s32, sbf>(g, m0, v, z, U, colour, nmr, z_zero, nrhs, vs, zs, rlist, s, C, red2);
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
 }

@@ -276,8 +276,10 @@ dw_status check_sap_params(const Geom& g, const sap_params* sp) {
                 sp->block[2], sp->block[3], g.B[0], g.B[1], g.B[2], g.B[3]);
       return DW_EINVAL;
     }
-  if (sp->ncycles < 0 || sp->nmr < 0 || sp->storage < 0 || sp->storage > 3) {
-    set_error("invalid sap_params (ncycles %d, nmr %d, storage %d)", sp->ncycles, sp->nmr, sp->storage);
+  if (sp->ncycles < 0 || sp->nmr < 0 || sp->storage < 0 || sp->storage > 3 || !(sp->mr_reduction >= 0.0) ||
+      !(sp->mr_reduction < 1.0)) {
+    set_error("invalid sap_params (ncycles %d, nmr %d, storage %d, mr_reduction %g)", sp->ncycles, sp->nmr,
+              sp->storage, sp->mr_reduction);
     return DW_EINVAL;
   }
   return DW_OK;
@@ -293,7 +295,7 @@ dw_status sap_apply_internal(dw_field f, double m0, const sap_params* sp, const 
   for (int cyc = 0; cyc < sp->ncycles; ++cyc)
     for (int colour = 0; colour < 2; ++colour)
       DW_TRY(launch_sap_colour(g, m0, prec, v, z, f->U[prec], colour, sp->nmr, cyc == 0 && colour == 0 ? 1 : 0, nrhs,
-                               n, n, stream, nullptr, f->C[prec]));
+                               n, n, stream, nullptr, f->C[prec], sp->mr_reduction));
   return DW_OK;
 }
 
@@ -341,6 +343,72 @@ extern "C" dw_status sap_precondition(dw_field f, double m0, const sap_params* s
     DW_TRY(sap_apply_internal(f, m0, sp, vi.p, zi.p, 1, stream));
     DW_TRY(launch_unpack_spinor(g, zprec, zi.p, zr, 1.0 / sigma, 1, stream));
   }
+  DW_CHECK_HIP(hipStreamSynchronize(stream));
+  return DW_OK;
+}
+
+extern "C" dw_status sap_solve(dw_field f, double m0, const sap_params* sp, const double* b, double* x, int32_t niter,
+                               double* resid, hipStream_t stream) {
+  clear_error();
+  if (!f || !b || !x || !resid || niter < 0 || b == x) {
+    set_error("sap_solve: invalid argument");
+    return DW_EINVAL;
+  }
+  DW_TRY(check_sap_params(f->g, sp));
+  DW_TRY(check_device(f->ctx));
+  ProfScope ps(f->ctx);
+  const Geom& g = f->g;
+  const long long n = g.V * 12;
+  const int prec = sp->storage;
+  const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
+  DevBuf bi, xi, ri, vi, zi, part, nrm, one;
+  DW_TRY(bi.alloc(f->ctx, (size_t)n * 16, stream));
+  DW_TRY(xi.alloc(f->ctx, (size_t)n * 16, stream));
+  DW_TRY(ri.alloc(f->ctx, (size_t)n * 16, stream));
+  DW_TRY(vi.alloc(f->ctx, (size_t)n * pair_bytes(prec), stream));
+  DW_TRY(zi.alloc(f->ctx, (size_t)n * pair_bytes(zprec), stream));
+  DW_TRY(part.alloc(f->ctx, (size_t)kBlasGrid * 16, stream));
+  DW_TRY(nrm.alloc(f->ctx, 16, stream));
+  DW_TRY(one.alloc(f->ctx, 16, stream));
+  static const double kOne[2] = {1.0, 0.0};
+  DW_CHECK_HIP(hipMemcpyAsync(one.p, kOne, sizeof kOne, hipMemcpyHostToDevice, stream));
+  DW_TRY(launch_pack_spinor(g, DW_PREC_F64, b, bi.p, 1.0, 1, stream));
+  DW_CHECK_HIP(hipMemsetAsync(xi.p, 0, (size_t)n * 16, stream));
+  auto sqnorm = [&](const void* v, double& out) -> dw_status {
+    DW_TRY(blas_dots(DW_PREC_F64, v, n, 1, (const double*)v, n, part.as<double>(), nrm.as<double>(), 1, 0, stream));
+    double h[2];
+    DW_CHECK_HIP(hipMemcpyAsync(h, nrm.p, sizeof h, hipMemcpyDeviceToHost, stream));
+    DW_CHECK_HIP(hipStreamSynchronize(stream));
+    out = h[0];
+    return DW_OK;
+  };
+  double bb;
+  DW_TRY(sqnorm(bi.p, bb));
+  if (!(bb > 0)) {
+    set_error("sap_solve: b = 0");
+    return DW_EINVAL;
+  }
+  const double bnorm = sqrt(bb);
+  for (int k = 0; k <= niter; ++k) {
+    // r = b - D x_k (FP64 links, clover and arithmetic)
+    DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, xi.p, 1.0, f->U[DW_PREC_F64], ri.as<double>(), bi.as<double>(), 1,
+                               1, n, n, stream, nullptr, f->C[DW_PREC_F64]));
+    double rr;
+    DW_TRY(sqnorm(ri.p, rr));
+    resid[k] = sqrt(rr) / bnorm;
+    if (rr == 0) {
+      for (int j = k + 1; j <= niter; ++j) resid[j] = 0;
+      break;
+    }
+    if (k == niter || sp->ncycles == 0) continue;  // M = 0 without cycles
+    // x_{k+1} = x_k + M r: the preconditioner input at storage precision,
+    // scaled to unit RMS (M is scale-equivariant), the correction added in FP64
+    const double sigma = prec == DW_PREC_F64 ? 1.0 : sqrt((double)n / rr);
+    DW_TRY(launch_convert(DW_PREC_F64, ri.p, prec, vi.p, sigma, n, stream));
+    DW_TRY(sap_apply_internal(f, m0, sp, vi.p, zi.p, 1, stream));
+    DW_TRY(blas_combine(zprec, zi.p, n, 1, one.as<double>(), 1.0 / sigma, xi.as<double>(), n, stream));
+  }
+  DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, xi.p, x, 1.0, 1, stream));
   DW_CHECK_HIP(hipStreamSynchronize(stream));
   return DW_OK;
 }

@@ -235,7 +235,7 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
           for (int colour = 0; colour < 2; ++colour)
             DW_TRY(launch_sap_colour(g, m0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
                                      cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, W.rlist.as<int>(),
-                                     f->C[prec]));
+                                     f->C[prec], P->sap.mr_reduction));
         if (zprec != DW_PREC_F64)
           for (int r : part)
             DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), DW_PREC_F64,

@@ -82,7 +82,7 @@ def test_tune_cache_roundtrip(tmp_path):
     assert len({k1, k2, k3}) == 3
     assert c.get(k1) is None
     tuned = P.SolverParams(m=24, k=8, tol=1e-10, sap=P.SapParams(block=(8, 4, 4, 4), ncycles=2, nmr=5,
-                                                                  storage=P.DW_PREC_F16))
+                                                                  storage=P.DW_PREC_F16, mr_reduction=0.1))
     c.put(k1, tuned, [{"block": [8, 4, 4, 4], "seconds": 1.0}])
     c.put(k3, base)
     assert c.get(k1) == tuned and c.get(k3) == base and c.get(k2) is None
@@ -90,3 +90,17 @@ def test_tune_cache_roundtrip(tmp_path):
     s = P.TuneSpace(blocks=((4, 4, 4, 4), (8, 4, 4, 4)), nmr=(3, 6), s=(1, 3), mk=((20, 5),), repeats=2)._c()
     assert s.nblocks == 2 and list(s.blocks[1]) == [8, 4, 4, 4] and (s.nmr_min, s.nmr_max) == (3, 6)
     assert s.nmk == 1 and list(s.mk[0]) == [20, 5] and s.repeats == 2
+
+
+def test_sap_params_layout():
+    """sap_params: four int32 extents, four int32 fields, then the double
+    mr_reduction at byte 32; it is embedded in fgmresdr_params."""
+    import ctypes
+
+    import paper_1204_5463_amd as P
+
+    assert ctypes.sizeof(P._SapParams) == 40 and P._SapParams.mr_reduction.offset == 32
+    p = P.SapParams(block=(4, 2, 2, 2), ncycles=3, nmr=7, mr_reduction=0.25)._c()
+    assert (p.ncycles, p.nmr, p.mr_reduction) == (3, 7, 0.25)
+    q = P._params_from_c(P.SolverParams(sap=P.SapParams(mr_reduction=0.1))._c())
+    assert q.sap.mr_reduction == 0.1
