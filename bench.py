@@ -492,6 +492,8 @@ def main():
                 params.flags = (params.flags & ~P.SOLVE_GRAPHS) | (P.SOLVE_GRAPHS if int(val) else 0)
             elif key == "v32":
                 params.flags = (params.flags & ~P.SOLVE_V32) | (P.SOLVE_V32 if int(val) else 0)
+            elif key == "inject":
+                params.flags = (params.flags & ~P.SOLVE_INJECT) | (P.SOLVE_INJECT if int(val) else 0)
             elif key == "red":
                 params.sap.mr_reduction = float(val)
             else:

@@ -117,8 +117,17 @@ typedef struct sap_params {
  *              stays FP64), which halves the Gram-Schmidt traffic; the
  *              Arnoldi relation then holds to FP32 accuracy and the explicit
  *              FP64 residual at every restart (Section 4.7) keeps the solve
- *              exact. Other bits must be 0. */
-enum { DW_SOLVE_GRAPHS = 1, DW_SOLVE_V32 = 2 };
+ *              exact.
+ *              DW_SOLVE_INJECT: at a deflated restart, bring the explicit
+ *              FP64 residual r into the new cycle in the two further places
+ *              Section 4.7 names: the last column of G_{k+1} is V_{m+1}^H r
+ *              instead of the small residual c - H^ eta, and v_{k+1} is r
+ *              orthonormalised against the rotated V_k (with the phase of the
+ *              rotated v_{k+1}, so that D Z_k = V_{k+1} H^_k keeps holding up
+ *              to the difference between the two residuals). In exact
+ *              arithmetic nothing changes; it is meant for a low-precision
+ *              basis (DW_SOLVE_V32). Other bits must be 0. */
+enum { DW_SOLVE_GRAPHS = 1, DW_SOLVE_V32 = 2, DW_SOLVE_INJECT = 4 };
 
 typedef struct fgmresdr_params {
   int32_t m;

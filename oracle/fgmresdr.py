@@ -12,7 +12,11 @@ Test infrastructure only. Follows the paper's Section 4:
     V_{k+1} = V Q_{k+1}, Z_k = Z Q_k (Alg. 4 and Section 4.5);
   * explicit FP64 residual once per cycle, injected into the right-hand
     side c = [V_{k+1}^H r; 0], and a clean restart (no deflation) when
-    ||r_explicit|| / ||r_implicit|| > t (Section 4.7).
+    ||r_explicit|| / ||r_implicit|| > t (Section 4.7);
+  * optionally (``inject``) the explicit residual also enters G_{k+1} in
+    place of the small residual c - H^ eta (as V_{m+1}^H r), and becomes the
+    last vector v_{k+1} after orthonormalisation against the rotated V_k,
+    as Section 4.7 does for its low-precision Arnoldi.
 
 Readings taken where the paper is silent:
   * m is the total basis size including the k deflation vectors; cycles
@@ -24,7 +28,11 @@ Readings taken where the paper is silent:
   * h_{j+1,j} <= 1e-14 ||H^|| is a breakdown that ends the cycle;
   * a singular H_m, a cycle too short to deflate (fewer than k + 1 steps)
     or a non-finite value leads to a clean restart;
-  * harmonic Ritz values are ordered by modulus with a stable sort.
+  * harmonic Ritz values are ordered by modulus with a stable sort;
+  * the injected v_{k+1} takes the phase of the rotated v_{k+1} it replaces
+    (the paper leaves the phase open; this choice keeps the coefficients of
+    A Z_k = V_{k+1} H^_k), orthogonalised by classical Gram-Schmidt with a
+    second pass; a zero or non-finite result keeps the rotated vector.
 """
 from __future__ import annotations
 
@@ -68,6 +76,21 @@ def harmonic_ritz(Hhat):
     return lam[order], G[:, order]
 
 
+def injected_vector(Vk, v_old, r):
+    """The explicit residual r orthonormalised against Vk (classical
+    Gram-Schmidt, two passes), with the phase of v_old (Section 4.7).
+    Returns v_old when r lies in span(Vk) (||w|| <= 1e-12 ||r||), or w is
+    orthogonal to v_old, or a value is not finite."""
+    w = r.copy()
+    for _ in range(2):
+        w = w - Vk @ (Vk.conj().T @ w)
+    wn = float(np.linalg.norm(w))
+    p = np.vdot(w, v_old)
+    if wn > 1e-12 * np.linalg.norm(r) and abs(p) > 0.0 and np.isfinite(wn) and np.isfinite(p):
+        return (p / abs(p)) * w / wn
+    return v_old
+
+
 def flexible_arnoldi(A, M, b, m):
     """Alg. 3: m steps from v_1 = b/||b||. Returns (V, Z, H)."""
     n = b.size
@@ -87,7 +110,7 @@ def flexible_arnoldi(A, M, b, m):
 
 
 def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
-             breakdown_tol=1e-14, keep_basis=False):
+             breakdown_tol=1e-14, keep_basis=False, inject=False):
     """Solve A x = b by FGMRES-DR(m, k) (Alg. 4) from x0 = 0.
 
     A, M: callables on flat complex vectors. M may change from call to call
@@ -183,12 +206,17 @@ def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
         ritz = lam
         Gk1 = np.zeros((jend + 1, k + 1), dtype=np.complex128)
         Gk1[:jend, :k] = G[:, :k]
-        Gk1[:, k] = c[:jend + 1] - Hc @ eta
+        if inject:
+            Gk1[:, k] = V[:, :jend + 1].conj().T @ r
+        else:
+            Gk1[:, k] = c[:jend + 1] - Hc @ eta
         Q, _ = np.linalg.qr(Gk1)
         Qk = Q[:jend, :k]
         Hk = Q.conj().T @ Hc @ Qk
         V[:, :k + 1] = V[:, :jend + 1] @ Q
         Z[:, :k] = Z[:, :jend] @ Qk
+        if inject:
+            V[:, k] = injected_vector(V[:, :k], V[:, k], r)
         V[:, k + 1:] = 0.0
         Z[:, k:] = 0.0
         H[:] = 0.0

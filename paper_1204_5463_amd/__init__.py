@@ -29,7 +29,7 @@ __all__ = [
 
 DW_OK, DW_EINVAL, DW_ENOMEM, DW_EHIP, DW_ENOTCONV, DW_EBUSY, DW_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 DW_PREC_F64, DW_PREC_F32, DW_PREC_F16, DW_PREC_BF16 = 0, 1, 2, 3
-SOLVE_GRAPHS, SOLVE_V32 = 1, 2
+SOLVE_GRAPHS, SOLVE_V32, SOLVE_INJECT = 1, 2, 4
 PREC_NAMES = {"f64": DW_PREC_F64, "f32": DW_PREC_F32, "f16": DW_PREC_F16, "bf16": DW_PREC_BF16}
 PAIR_BYTES = {DW_PREC_F64: 16, DW_PREC_F32: 8, DW_PREC_F16: 4, DW_PREC_BF16: 4}
 
@@ -143,7 +143,9 @@ class SolverParams:
     restart_t: float = 5.0
     sap: SapParams = dataclasses.field(default_factory=SapParams)
     shared_defl: int = 0
-    flags: int = 0  # SOLVE_GRAPHS: replay captured steps (single RHS, non-default stream); SOLVE_V32: FP32 basis
+    # SOLVE_GRAPHS: replay captured steps (single RHS, non-default stream); SOLVE_V32: FP32 basis;
+    # SOLVE_INJECT: explicit residual also in G_{k+1} and v_{k+1} at deflated restarts (Section 4.7)
+    flags: int = 0
 
     def _c(self):
         p = _SolverParams()

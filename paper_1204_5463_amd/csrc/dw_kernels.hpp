@@ -21,6 +21,8 @@ dw_status blas_sub_cols(const double* V, long long stride, int ncols, const doub
                         hipStream_t s);
 // y = alpha[0] * x (alpha a device double)
 dw_status blas_scale(const double* x, double* y, const double* alpha, long long n, hipStream_t s);
+// x *= alpha[0] in place (alpha a device complex pair)
+dw_status blas_scale_c(double* x, const double* alpha, long long n, hipStream_t s);
 // x += scale * sum_c coef_c Z_c
 dw_status blas_combine(int prec_z, const void* Z, long long stride, int ncols, const double* coef, double scale,
                        double* x, long long n, hipStream_t s);

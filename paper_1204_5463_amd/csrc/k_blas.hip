@@ -116,6 +116,13 @@ __global__ void __launch_bounds__(kThreads)
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) st(y + i, a * ld<double>(x + i));
 }
 
+// x *= alpha (complex, device)
+__global__ void __launch_bounds__(kThreads) k_scale_c(s64* __restrict__ x, const s64* __restrict__ alpha, long long n) {
+  const cplx<double> a = ld<double>(alpha);
+  const long long step = (long long)gridDim.x * kThreads;
+  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) st(x + i, a * ld<double>(x + i));
+}
+
 // x += scale * sum_c coef[c] Z_c
 template <typename SZ>
 __global__ void __launch_bounds__(kThreads)
@@ -348,6 +355,14 @@ dw_status blas_scale(const double* x, double* y, const double* alpha, long long 
   hipLaunchKernelGGL(k_scale, grid_for(n), kThreads, 0, s, (const s64*)x, (s64*)y, alpha, n);
   DW_CHECK_LAUNCH();
   kt.done((double)n * 32, (double)n * 2);
+  return DW_OK;
+}
+
+dw_status blas_scale_c(double* x, const double* alpha, long long n, hipStream_t s) {
+  KTimer kt(DW_K_SCALE, s);
+  hipLaunchKernelGGL(k_scale_c, grid_for(n), kThreads, 0, s, (s64*)x, (const s64*)alpha, n);
+  DW_CHECK_LAUNCH();
+  kt.done((double)n * 32, (double)n * 6);
   return DW_OK;
 }
 

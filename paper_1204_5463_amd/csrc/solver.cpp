@@ -27,7 +27,10 @@
 // Per cycle: eta, x += Z eta, explicit FP64 residual r = b - D x; stop, or
 // clean restart if ||r|| / ||r_implicit|| > t, or deflated restart:
 // harmonic Ritz pairs, Q_{k+1}, V <- V Q_{k+1}, Z <- Z Q_k, H^_k, and
-// c = [V_{k+1}^H r; 0] with the explicit residual r.
+// c = [V_{k+1}^H r; 0] with the explicit residual r. With DW_SOLVE_INJECT the
+// explicit residual also gives G_{k+1}'s last column (V^H r) and v_{k+1}
+// (r orthonormalised against the rotated V_k, phase-matched to the rotated
+// v_{k+1}), as Section 4.7 does for its low-precision Arnoldi.
 #include <math.h>
 #include <string.h>
 
@@ -52,9 +55,10 @@ namespace {
 struct Work {
   int nr = 0, m = 0;
   long long n = 0;
-  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal, rlist, proj;
+  DevBuf V, Z, zs, w, r, x, b, vs, partials, H, c, eta, red, coef, nrm, Q, ritz, scal, rlist, proj, inj, zeta;
   double* scal_h = nullptr;  // nr x (kSclCount + 2): scalars and the pair nrm
   int* rlist_h = nullptr;
+  double* inj_h = nullptr;  // nr x 4 doubles: v_{k+1}^H w and ||w||^2 of the injection, then its coefficient
   // captured Arnoldi steps, indexed by 2 j + lagged (single-RHS batches)
   std::vector<hipGraphExec_t> graphs;
   ~Work() {
@@ -62,6 +66,7 @@ struct Work {
       if (g) (void)hipGraphExecDestroy(g);
     if (scal_h) (void)hipHostFree(scal_h);
     if (rlist_h) (void)hipHostFree(rlist_h);
+    if (inj_h) (void)hipHostFree(inj_h);
   }
   int vprec = DW_PREC_F64;  // storage of the Krylov basis V
   // basis of RHS r, and its column j
@@ -82,6 +87,9 @@ struct Work {
   const double* sh(int r) const { return scal_h + (long long)r * (kSclCount + 2); }
   // shared-deflation projection: t = V_0^H r (kLd pairs), y (kMaxM), s = H_0 y (kLd)
   double* projr(int r) const { return proj.as<double>() + 2 * (long long)r * (2 * kLd + kMaxM); }
+  // residual injection: G column V^H r (kLd pairs), t = V_k^H w (kLd), then
+  // 4 pairs: v_{k+1}^H w, ||w||^2, coefficient
+  double* injr(int r) const { return inj.as<double>() + 2 * (long long)r * (2 * kLd + 4); }
 };
 
 int basis_prec(const fgmresdr_params* P) { return (P->flags & DW_SOLVE_V32) ? DW_PREC_F32 : DW_PREC_F64; }
@@ -120,6 +128,12 @@ dw_status alloc_work(dw_field f, const fgmresdr_params* P, int nr, Work& W, hipS
   DW_TRY(W.ritz.alloc(ctx, (size_t)nr * kMaxM * 16, s));
   DW_TRY(W.scal.alloc(ctx, (size_t)nr * kSclCount * 8, s));
   if (P->shared_defl && nr > 1) DW_TRY(W.proj.alloc(ctx, (size_t)nr * (2 * kLd + kMaxM) * 16, s));
+  if (P->flags & DW_SOLVE_INJECT) {
+    DW_TRY(W.inj.alloc(ctx, (size_t)nr * (2 * kLd + 4) * 16, s));
+    DW_TRY(W.zeta.alloc(ctx, (size_t)kMaxM * 16, s));
+    DW_CHECK_HIP(hipMemsetAsync(W.zeta.p, 0, (size_t)kMaxM * 16, s));
+    DW_CHECK_HIP(hipHostMalloc((void**)&W.inj_h, (size_t)nr * 4 * sizeof(double), hipHostMallocDefault));
+  }
   DW_TRY(W.rlist.alloc(ctx, (size_t)nr * sizeof(int), s));
   DW_CHECK_HIP(hipHostMalloc((void**)&W.scal_h, (size_t)nr * (kSclCount + 2) * sizeof(double), hipHostMallocDefault));
   DW_CHECK_HIP(hipHostMalloc((void**)&W.rlist_h, (size_t)nr * sizeof(int), hipHostMallocDefault));
@@ -144,6 +158,58 @@ dw_status readback(Work& W, hipStream_t s) {
 dw_status set_rlist(Work& W, const std::vector<int>& list, hipStream_t s) {
   for (size_t i = 0; i < list.size(); ++i) W.rlist_h[i] = list[i];
   DW_CHECK_HIP(hipMemcpyAsync(W.rlist.p, W.rlist_h, list.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  return DW_OK;
+}
+
+// v_{k+1} from the explicit residual r (Section 4.7): w = r orthogonalised
+// against the rotated V_k (classical Gram-Schmidt, two passes), then
+// v_{k+1} = e^{i theta} w / ||w|| with the phase of the rotated v_{k+1}
+// (e^{i theta} = w^H v_{k+1} / |w^H v_{k+1}|), so that D Z_k = V_{k+1} H^_k
+// keeps its coefficients. The rotated vector is kept when r lies in
+// span(V_k) (||w|| <= 1e-12 ||r||), w is orthogonal to it, or a value is not
+// finite. rnorm: ||r|| per entry of rot. Uses W.w as scratch; one
+// synchronisation for the batch.
+dw_status inject_residual(Work& W, const std::vector<int>& rot, const std::vector<double>& rnorm, int k,
+                          hipStream_t s) {
+  const long long n = W.n;
+  for (size_t i = 0; i < rot.size(); ++i) {
+    const int r = rot[i];
+    double* w = W.vec(W.w, r);
+    double* t = W.injr(r) + 2 * kLd;
+    double* tail = W.injr(r) + 4 * kLd;
+    DW_CHECK_HIP(hipMemcpyAsync(w, W.vec(W.r, r), (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+    for (int pass = 0; pass < 2; ++pass) {
+      DW_TRY(blas_dots(W.vprec, W.Vr(r), n, k, w, n, W.partr(r), t, 1, 0, s));
+      DW_TRY(blas_combine(W.vprec, W.Vr(r), n, k, t, -1.0, w, n, s));
+    }
+    DW_TRY(blas_dots(W.vprec, W.Vc(r, k), n, 1, w, n, W.partr(r), tail, 1, 0, s));
+    DW_TRY(blas_dots(DW_PREC_F64, w, n, 1, w, n, W.partr(r), tail + 2, 1, 0, s));
+    DW_CHECK_HIP(hipMemcpyAsync(W.inj_h + 4 * (long long)i, tail, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  DW_CHECK_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < rot.size(); ++i) {
+    const int r = rot[i];
+    double* h = W.inj_h + 4 * (long long)i;
+    // h[0] + i h[1] = v_{k+1}^H w, h[2] = ||w||^2
+    const double pm = hypot(h[0], h[1]), wn = sqrt(h[2]);
+    if (!(pm > 0) || !(wn > 1e-12 * rnorm[i]) || !std::isfinite(pm) || !std::isfinite(wn)) continue;
+    // coefficient e^{i theta} / ||w|| with e^{i theta} = conj(v^H w) / |v^H w|
+    h[0] = h[0] / (pm * wn);
+    h[1] = -h[1] / (pm * wn);
+    double* coef = W.injr(r) + 4 * kLd + 4;
+    DW_CHECK_HIP(hipMemcpyAsync(coef, h, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    double* w = W.vec(W.w, r);
+    if (W.vprec == DW_PREC_F64) {
+      DW_CHECK_HIP(hipMemsetAsync(W.Vc(r, k), 0, (size_t)n * 16, s));
+      DW_TRY(blas_combine(DW_PREC_F64, w, n, 1, coef, 1.0, (double*)W.Vc(r, k), n, s));
+    } else {
+      // w <- coefficient * w in place (FP64), then stored at the basis precision
+      DW_TRY(blas_scale_c(w, coef, n, s));
+      DW_TRY(launch_convert(DW_PREC_F64, w, W.vprec, W.Vc(r, k), 1.0, n, s));
+    }
+  }
+  // the pinned coefficients stay in use until the copies above have run
+  DW_CHECK_HIP(hipStreamSynchronize(s));
   return DW_OK;
 }
 
@@ -356,10 +422,21 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         defl.push_back(r);
       }
     }
+    const bool inject = (P->flags & DW_SOLVE_INJECT) != 0;
     if (!defl.empty()) {
-      for (int r : defl)
-        DW_TRY(dense_deflate(W.Hr(r), R[r].jend, k, W.cr(r), W.etar(r), W.Qr(r), W.ritzr(r), W.scalr(r), s));
+      for (int r : defl) {
+        if (inject) {
+          // G_{k+1}'s last column from the explicit residual: V_{m+1}^H r with
+          // eta = 0 (the kernel forms c - H^ eta)
+          DW_TRY(blas_dots(W.vprec, W.Vr(r), n, R[r].jend + 1, W.vec(W.r, r), n, W.partr(r), W.injr(r), 1, 0, s));
+          DW_TRY(dense_deflate(W.Hr(r), R[r].jend, k, W.injr(r), W.zeta.as<double>(), W.Qr(r), W.ritzr(r),
+                               W.scalr(r), s));
+        } else {
+          DW_TRY(dense_deflate(W.Hr(r), R[r].jend, k, W.cr(r), W.etar(r), W.Qr(r), W.ritzr(r), W.scalr(r), s));
+        }
+      }
       DW_TRY(readback(W, s));
+      std::vector<int> rot;
       for (int r : defl) {
         Rhs& q = R[r];
         if (W.sh(r)[kSclStatus] != 0.0) {
@@ -370,6 +447,15 @@ dw_status solve_batch(dw_field f, double m0, const fgmresdr_params* P, const dou
         if (r == 0) donor_ok = true;
         DW_TRY(blas_rotate(W.vprec, W.Vr(r), n, q.jend + 1, W.Qr(r), kLd, k + 1, n, s));
         DW_TRY(blas_rotate(DW_PREC_F64, W.Zr(r), n, q.jend, W.Qr(r), kLd, k, n, s));
+        rot.push_back(r);
+      }
+      if (inject && !rot.empty()) {
+        std::vector<double> rnorm;
+        for (int r : rot) rnorm.push_back(R[r].res_e);
+        DW_TRY(inject_residual(W, rot, rnorm, k, s));
+      }
+      for (int r : rot) {
+        Rhs& q = R[r];
         DW_CHECK_HIP(hipMemsetAsync(W.cr(r), 0, (size_t)kLd * 16, s));
         DW_TRY(blas_dots(W.vprec, W.Vr(r), n, k + 1, W.vec(W.r, r), n, W.partr(r), W.cr(r), 1, 0, s));
         q.fresh = false;
@@ -418,7 +504,7 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
     return DW_EINVAL;
   }
   DW_TRY(check_sap_params(f->g, &P->sap));
-  if (P->flags & ~(DW_SOLVE_GRAPHS | DW_SOLVE_V32)) {
+  if (P->flags & ~(DW_SOLVE_GRAPHS | DW_SOLVE_V32 | DW_SOLVE_INJECT)) {
     set_error("fgmresdr_solve: unknown flags 0x%x", (unsigned)P->flags);
     return DW_EINVAL;
   }

@@ -198,7 +198,7 @@ def test_graph_captured_steps_equal_eager(c1):
     prm.flags = 0
     x1, _ = f.solve(M01, prm, P.to_device(b))
     assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
-    prm.flags = 4
+    prm.flags = 8
     with pytest.raises(P.DwError):
         f.solve(M01, prm, P.to_device(b))
 
@@ -212,6 +212,41 @@ def test_fp32_basis_reaches_fp64_residual(c1, prec):
     prm = _params(prec, m=12, k=4)
     _, s64 = f.solve(M01, prm, P.to_device(b))
     prm.flags = P.SOLVE_V32
+    x, st = f.solve(M01, prm, P.to_device(b))
+    x = x.cpu().numpy()
+    assert st[0].converged
+    r = b - W.apply_D(U, M01, x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert st[0].iterations <= 1.5 * s64[0].iterations + 12
+
+
+def test_residual_injection_follows_oracle(c1):
+    """SOLVE_INJECT (Section 4.7: the explicit residual in G_{k+1} and v_{k+1}):
+    the all-FP64 solve follows the oracle's injected FGMRES-DR."""
+    U, b, f, xo, info = c1
+    shp = b.shape
+    A = lambda v: W.apply_D(U, M01, v.reshape(shp)).reshape(-1)
+    M = lambda v: S.sap(U, M01, L1, B1, 1, 4, v.reshape(shp)).reshape(-1)
+    xi, ii = F.fgmresdr(A, M, b.reshape(-1), 20, 5, tol=1e-10, max_iter=2000, inject=True)
+    prm = _params()
+    prm.flags = P.SOLVE_INJECT
+    x, st = f.solve(M01, prm, P.to_device(b))
+    x = x.cpu().numpy()
+    assert st[0].converged and ii.converged and ii.cycles >= 3
+    assert abs(st[0].iterations - ii.iterations) <= 1, (st[0].iterations, ii.iterations)
+    assert st[0].clean_restarts == ii.clean_restarts == 0
+    assert np.linalg.norm(x - xi.reshape(shp)) <= 1e-8 * np.linalg.norm(xi)
+
+
+@pytest.mark.parametrize("prec", [P.DW_PREC_F16, P.DW_PREC_F64])
+def test_fp32_basis_with_injection(c1, prec):
+    """The paper's low-precision Arnoldi arrangement: FP32 basis plus the
+    explicit FP64 residual injected at every deflated restart."""
+    U, b, f, xo, info = c1
+    prm = _params(prec, m=12, k=4)
+    _, s64 = f.solve(M01, prm, P.to_device(b))
+    prm.flags = P.SOLVE_V32 | P.SOLVE_INJECT
     x, st = f.solve(M01, prm, P.to_device(b))
     x = x.cpu().numpy()
     assert st[0].converged

@@ -17,7 +17,10 @@ paper and the mathematics fix:
   * clean restarts at every cycle reduce FGMRES-DR to FGMRES(m);
   * a happy breakdown for an eigenvector right-hand side;
   * the converged solution against dense LU, gauge covariance of the whole
-    solve, and non-convergence reporting.
+    solve, and non-convergence reporting;
+  * the injected v_{k+1} (Section 4.7): unit, orthogonal to V_k, r in
+    span(V_k, v_{k+1}), phase of the replaced vector; with an exact Arnoldi
+    the injected solve follows the plain one to rounding.
 """
 import numpy as np
 import pytest
@@ -232,3 +235,38 @@ def test_nonconvergence_is_reported():
     assert 1e-10 < info.true_relres < 1.0
     with pytest.raises(ValueError):
         F.fgmresdr(A, M, b, 5, 5)
+
+
+def test_injected_vector_properties():
+    rng = np.random.default_rng(5)
+    n, k = 60, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k + 1)) + 1j * rng.standard_normal((n, k + 1)))
+    Vk, v_old = Q[:, :k], Q[:, k]
+    # r in span(V_k, v_old) plus a small perturbation, as after a drift
+    r = Vk @ (rng.standard_normal(k) + 1j * rng.standard_normal(k)) + (0.7 - 0.4j) * v_old
+    r = r + 1e-3 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    v = F.injected_vector(Vk, v_old, r)
+    assert abs(np.linalg.norm(v) - 1) < 1e-14
+    assert np.max(np.abs(Vk.conj().T @ v)) < 1e-14
+    Vn = np.concatenate([Vk, v[:, None]], axis=1)
+    assert np.linalg.norm(r - Vn @ (Vn.conj().T @ r)) < 1e-13 * np.linalg.norm(r)
+    p = np.vdot(v, v_old)
+    assert abs(p.imag) < 1e-14 and p.real > 0.99
+    # r in span(V_k): the rotated vector is kept
+    assert np.array_equal(F.injected_vector(Vk, v_old, Vk @ np.ones(k)), v_old)
+
+
+def test_injection_follows_plain_solve_in_fp64():
+    L = (4, 4, 4, 4)
+    U, A, M = _ops(L, 0.3, 0, -0.21)
+    b = synth.gaussian_spinor(L, 1000).reshape(-1)
+    x0, i0 = F.fgmresdr(A, M, b, 20, 5, tol=1e-10)
+    x1, i1 = F.fgmresdr(A, M, b, 20, 5, tol=1e-10, inject=True)
+    assert i0.converged and i1.converged and i0.cycles >= 3
+    assert abs(i0.iterations - i1.iterations) <= 1 and i1.clean_restarts == i0.clean_restarts
+    h0 = np.array([r for _, r in i0.history])
+    h1 = np.array([r for _, r in i1.history])
+    nh = min(len(h0), len(h1))
+    assert np.max(np.abs(h0[:nh] - h1[:nh]) / h0[:nh]) < 1e-6
+    assert np.linalg.norm(x0 - x1) < 1e-9 * np.linalg.norm(x0)
+
