@@ -168,6 +168,21 @@ __device__ __forceinline__ void hop_dispatch(int h, cplx<T> acc[12], PsiF&& psi,
 typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 
+// First term of a dot-product chain, a.x b.x + a.y b.y in FP32. Written as
+// the three-operand form with an inline zero addend: the builtin with a zero
+// addend becomes a register copy of 0 plus the two-operand accumulate form,
+// one extra VALU instruction per chain (12 per hop).
+__device__ __forceinline__ float dot2_first(h2v a, h2v b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float dot2_first(b2v a, b2v b) {
+  float r;
+  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 template <typename SG>
 struct link16;
 template <>
@@ -181,6 +196,7 @@ struct link16<s16> {
   }
   static __device__ __forceinline__ V raw(const s16* p) { return *reinterpret_cast<const V*>(p); }
   static __device__ __forceinline__ float dot(V a, V b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+  static __device__ __forceinline__ float dot0(V a, V b) { return dot2_first(a, b); }
 };
 template <>
 struct link16<sbf> {
@@ -195,6 +211,7 @@ struct link16<sbf> {
   static __device__ __forceinline__ float dot(V a, V b, float c) {
     return __builtin_amdgcn_fdot2_f32_bf16(a, b, c, false);
   }
+  static __device__ __forceinline__ float dot0(V a, V b) { return dot2_first(a, b); }
 };
 
 template <typename SG>
@@ -225,9 +242,10 @@ __device__ __forceinline__ void hop16(cplx<float> acc[12], PsiF&& psi, UF&& u) {
   cplx<float> g0[3], g1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
+    const V w0 = u(DIR > 0 ? a * 3 : a);
+    float r0 = L::dot0(w0, a0[0]), i0 = L::dot0(w0, b0[0]), r1 = L::dot0(w0, a1[0]), i1 = L::dot0(w0, b1[0]);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
+    for (int b = 1; b < 3; ++b) {
       const V w = u(DIR > 0 ? a * 3 + b : b * 3 + a);
       r0 = L::dot(w, a0[b], r0);
       i0 = L::dot(w, b0[b], i0);
@@ -281,9 +299,11 @@ __device__ __forceinline__ void hop16p(cplx<float> acc[12], PsiF&& psi, UF&& u) 
   cplx<float> g0[3], g1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
+    const h2v w0 = u(DIR > 0 ? a * 3 : a);
+    float r0 = dot2_first(w0, a0[0]), i0 = dot2_first(w0, b0[0]), r1 = dot2_first(w0, a1[0]),
+          i1 = dot2_first(w0, b1[0]);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
+    for (int b = 1; b < 3; ++b) {
       const h2v w = u(DIR > 0 ? a * 3 + b : b * 3 + a);
       r0 = __builtin_amdgcn_fdot2(w, a0[b], r0, false);
       i0 = __builtin_amdgcn_fdot2(w, b0[b], i0, false);

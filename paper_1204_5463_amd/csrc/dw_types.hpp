@@ -43,6 +43,21 @@ __host__ __device__ __forceinline__ cplx<T> cdot(cplx<T> a, cplx<T> b) {
 }
 template <typename T>
 __host__ __device__ __forceinline__ T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
+// acc += a b and acc -= a b as four fused multiply-adds (one rounding per term)
+template <typename T>
+__host__ __device__ __forceinline__ void cmac(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ void cmsub(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.re = fma(-a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(-a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
 // multiply by +i and -i
 template <typename T>
 __host__ __device__ __forceinline__ cplx<T> mul_i(cplx<T> a) { return {-a.im, a.re}; }

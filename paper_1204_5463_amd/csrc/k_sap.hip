@@ -100,6 +100,7 @@ __global__ void __launch_bounds__(MAXT)
   const SV* vr = v + (long long)rhs * vs;
   SZ* zr = z + (long long)rhs * zs;
   const T half = (T)0.5;
+  const T diag2 = diag + diag;
 
   // this block's spinors and links (contiguous chunks of the tiled layout)
   const SV* vb = vr + (long long)b * 12 * bvol;
@@ -205,14 +206,19 @@ __global__ void __launch_bounds__(MAXT)
         clover_acc_f<T>(Cl + (long long)b * kCloverPairs * bvol + cofs, bvol, l,
                         [&](int c) { return rho_s[c * bvol + l]; }, (T)-2, p);
       }
+      // p2 = 2 D^l rho = 2 diag rho - hops: the factor 2 cancels in the
+      // residual update (alpha p = alpha2 p2 with alpha2 = (p2^H rho)/(p2^H p2))
+      // and is restored in the iterate update, which saves the 1/2 scaling
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const cplx<T> r = rho_s[c * bvol + l];
-        p[c] = diag * r - half * p[c];
-        cplx<T> d = cdot(p[c], r);
-        nre += d.re;
-        nim += d.im;
-        den += norm2(p[c]);
+        p[c] = mk<T>(fma(diag2, r.re, -p[c].re), fma(diag2, r.im, -p[c].im));
+        nre = fma(p[c].re, r.re, nre);
+        nre = fma(p[c].im, r.im, nre);
+        nim = fma(p[c].re, r.im, nim);
+        nim = fma(-p[c].im, r.re, nim);
+        den = fma(p[c].re, p[c].re, den);
+        den = fma(p[c].im, p[c].im, den);
       }
     }
     nre = wave_sum(nre);
@@ -232,13 +238,15 @@ __global__ void __launch_bounds__(MAXT)
       den += rb[w * 3 + 2];
     }
     const cplx<T> alpha = den > (T)0 ? mk<T>(nre / den, nim / den) : mk<T>(0, 0);
+    const cplx<T> alpha_y = mk<T>(alpha.re + alpha.re, alpha.im + alpha.im);
     if (adapt && den > (T)0) rr -= (nre * nre + nim * nim) / den;
     if (active) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const cplx<T> r = rho_s[c * bvol + l];
-        y[c] += alpha * r;
-        put_rho(c, l, r - alpha * p[c]);
+        cplx<T> r = rho_s[c * bvol + l];
+        cmac(y[c], alpha_y, r);
+        cmsub(r, alpha, p[c]);
+        put_rho(c, l, r);
       }
     }
   }
