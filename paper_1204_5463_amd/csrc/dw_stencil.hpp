@@ -447,4 +447,42 @@ __device__ __forceinline__ void hop_sum_staged(const Geom& g, int b, int l, cons
   }
 }
 
+// In-block hopping sum of D^l (eq. 2) for compile-time BS^4 blocks, with
+// the link loads one hop ahead: per direction the backward hop's links are
+// loaded before the forward hop's arithmetic and the next direction's
+// forward links before the backward hop's, so each hop's L1/L2 latency
+// overlaps the previous hop's work. Sites on the lower face load their own
+// link in place of the (skipped) backward one, which keeps every load inside
+// the block. u_blk(mu, e, local site) returns a link entry as the hop takes it.
+template <typename T, typename SG, int BS, typename XB, typename UB>
+__device__ __forceinline__ void hop_sum_block_ahead(int l, XB&& xin_blk, UB&& u_blk, cplx<T> acc[12]) {
+  static_assert(BS > 0 && (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
+  constexpr int LB = ilog2(BS);
+  using W = decltype(u_blk(0, 0, 0));
+  auto dispatch = [&](int h, auto&& psi, auto&& u) {
+    if constexpr (std::is_same<SG, h2v>::value) hop16p_dispatch(h, acc, psi, u);
+    else if constexpr (is_link16<SG>) hop16_dispatch<SG>(h, acc, psi, u);
+    else hop_dispatch<T>(h, acc, psi, u);
+  };
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+  W wf[9], wb[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) wf[e] = u_blk(0, e, l);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const int st = 1 << (LB * mu);
+    const int lcm = (l >> (LB * mu)) & (BS - 1);
+    const int ub = lcm > 0 ? l - st : l;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) wb[e] = u_blk(mu, e, ub);
+    if (lcm < BS - 1) dispatch(2 * mu, [&](int k) { return xin_blk(l + st, k); }, [&](int e) { return wf[e]; });
+    if (mu < 3) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) wf[e] = u_blk(mu + 1, e, l);
+    }
+    if (lcm > 0) dispatch(2 * mu + 1, [&](int k) { return xin_blk(l - st, k); }, [&](int e) { return wb[e]; });
+  }
+}
+
 }  // namespace dw

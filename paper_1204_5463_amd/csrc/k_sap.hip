@@ -189,7 +189,14 @@ __global__ void __launch_bounds__(MAXT)
     cplx<T> p[12];
     T nre = 0, nim = 0, den = 0;
     if (active) {
-      if constexpr (P16)
+      // links loaded one hop ahead where the registers allow it without
+      // losing occupancy (16-bit links, no clover term)
+      constexpr bool AHEAD = BS > 0 && L16 && !CLOV;
+      if constexpr (AHEAD && P16)
+        hop_sum_block_ahead<T, h2v, BS>(l, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk, p);
+      else if constexpr (AHEAD)
+        hop_sum_block_ahead<T, LK, BS>(l, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk, p);
+      else if constexpr (P16)
         hop_sum_staged<T, false, h2v, BS>(
             g, b, l, bc, lc, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,
             [&](int, int, int) { return h2v{0, 0}; }, u_halo, p);
