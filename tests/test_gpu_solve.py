@@ -116,8 +116,9 @@ def test_multi_rhs_matches_single(c1):
     assert np.linalg.norm(x1.cpu().numpy() - x[1]) <= 1e-9 * np.linalg.norm(x[1])
 
 
-@pytest.mark.parametrize("prec", [P.DW_PREC_F64, P.DW_PREC_F16])
-def test_lockstep_batch_equals_single_solves(c1, prec):
+@pytest.mark.parametrize("prec,flags", [(P.DW_PREC_F64, 0), (P.DW_PREC_F16, 0),
+                                        (P.DW_PREC_F16, P.SOLVE_V32 | P.SOLVE_INJECT)])
+def test_lockstep_batch_equals_single_solves(c1, prec, flags):
     """RHS solved in lock-step share launches but not arithmetic: each must
     equal its own single-RHS solve bit for bit (a zero RHS, an easy and a
     harder one, so that RHS leave the batch at different times)."""
@@ -125,6 +126,7 @@ def test_lockstep_batch_equals_single_solves(c1, prec):
     b2 = synth.point_source_noise(L1, 5, seed=77)
     bb = np.stack([b, np.zeros_like(b), b2, 3.0 * synth.gaussian_spinor(L1, 1009)])
     prm = _params(prec, m=12, k=4)
+    prm.flags = flags
     x, st = f.solve(M01, prm, P.to_device(bb))
     x = x.cpu().numpy()
     assert st[1].converged and st[1].iterations == 0 and np.count_nonzero(x[1]) == 0
