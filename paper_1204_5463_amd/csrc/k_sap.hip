@@ -66,8 +66,16 @@ __device__ __forceinline__ T wave_sum(T a) {
 // link strides become immediates, local coordinates bit fields).
 // CLOV: the operator includes the clover term Cl (site-local, dw_clover.hpp),
 // in the residual and in every MR step.
+// FP32 arithmetic without the clover term: ask for four waves per SIMD
+// (at most 128 VGPRs), which keeps two 512-thread workgroups per CU; the
+// other variants need more registers and take what they need.
+template <typename T, bool CLOV>
+constexpr int sap_waves_per_simd() {
+  return std::is_same<T, float>::value && !CLOV ? 4 : 1;
+}
+
 template <typename T, typename SV, typename SZ, typename SG, int MAXT, bool LDSL, int BS, bool CLOV>
-__global__ void __launch_bounds__(MAXT)
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_waves_per_simd<T, CLOV>())))
     k_sap_colour(Geom g, int colour, T diag, const SV* __restrict__ v, SZ* __restrict__ z, const SG* __restrict__ U,
                  int nmr, int z_zero, long long vs, long long zs, int nr, const int* __restrict__ rlist,
                  const SG* __restrict__ Cl, T red2) {
