@@ -34,12 +34,14 @@ FP64_VALU_PEAK_TFLOPS = 78.6
 WORKLOADS = {
     # name: lattice, eps, gauge seed, mass spec, SAP, solver
     # FGMRES-DR(30, 12) as specified for this lattice; the SAP parameters
-    # (4^4 blocks, 8 cycles, 9 MR steps) are the time-to-solution optimum
-    # found by dw_autotune on this system (nMR 4..12, s 2..8, all block
-    # shapes with extents 2/4/8); the starting point s = 2, nMR = 5 needs
-    # 152 iterations and 2.3x the time
+    # (4^4 blocks, 13 cycles, 8 MR steps) are the time-to-solution optimum
+    # found by dw_autotune on this system (4^4 blocks, nMR 6..14, s 4..16;
+    # an earlier search over all block shapes with extents 2/4/8 picked 4^4);
+    # s = 8, nMR = 9, the optimum of a search capped at s = 8, needs 37
+    # iterations and 6% more time; the starting point s = 2, nMR = 5 needs
+    # 152 iterations and 2.5x the time
     "32^3x64": dict(L=(32, 32, 32, 64), eps=0.7, seed=0, mass=(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
-                    block=(4, 4, 4, 4), ncycles=8, nmr=9, storage="f16", m=30, k=12),
+                    block=(4, 4, 4, 4), ncycles=13, nmr=8, storage="f16", m=30, k=12),
     "16^3x32": dict(L=(16, 16, 16, 32), eps=0.6, seed=0, mass=(("16^3x32_eps0.6", "12^4_eps0.6"), 0.001),
                     block=(4, 4, 4, 4), ncycles=2, nmr=5, storage="f32", m=30, k=10),
     "8^4": dict(L=(8, 8, 8, 8), eps=0.3, seed=0, mass=(None, -0.1),
@@ -503,7 +505,7 @@ def main():
         log("[bench] autotuning (untimed)")
         ts = time.perf_counter()
         # the workload fixes FGMRES-DR(m, k); the SAP parameters are tuned
-        space = P.TuneSpace(nmr=(4, 12), s=(2, 8), passes=2, iter_cap=2.0)
+        space = P.TuneSpace(nmr=(4, 14), s=(2, 16), passes=2, iter_cap=2.0)
         params, trials = P.autotune(ctx, L, Ud, m0, params, bt, space=space, cache=P.TuneCache(args.autotune),
                                     csw=args.csw or wl.get("csw", 0.0))
         for t in trials:

@@ -51,7 +51,7 @@ def _window(a, shift):
 def test_sap_full_size_sampled_blocks(big, prec, tol):
     U, f, m0 = big
     v = synth.gaussian_spinor(L, 1000)
-    nmr = 9
+    nmr = 8
     z = f.sap(m0, P.SapParams(block=B, ncycles=1, nmr=nmr, storage=prec), P.to_device(v)).cpu().numpy()
     # window origin in blocks (7, 3, 1, 15): even coordinate sum keeps the colours; wraps in x and t
     shift = (28, 12, 4, 60)
@@ -73,7 +73,7 @@ def test_solve_full_size_true_residual(big, flags):
     U, f, m0 = big
     b = synth.gaussian_spinor(L, 1000)
     prm = P.SolverParams(m=30, k=12, max_iter=2000, tol=1e-10, flags=flags,
-                         sap=P.SapParams(block=B, ncycles=8, nmr=9, storage=P.DW_PREC_F16))
+                         sap=P.SapParams(block=B, ncycles=13, nmr=8, storage=P.DW_PREC_F16))
     x, st = f.solve(m0, prm, P.to_device(b))
     assert st[0].converged and st[0].true_relres <= 1e-10
     x = x.cpu().numpy()
