@@ -257,7 +257,8 @@ def serve(args):
     def params(storage, graphs=False):
         return P.SolverParams(m=30, k=12, tol=1e-10, restart_t=5.0, max_iter=20000,
                               flags=P.SOLVE_GRAPHS if graphs else 0,
-                              sap=P.SapParams(block=(4, 4, 4, 4), ncycles=6, nmr=8, storage=storage))
+                              sap=P.SapParams(block=(4, 4, 4, 4), ncycles=args.serve_cycles, nmr=8,
+                                              storage=storage))
 
     ctx = P.Context(0)
     # warm the kernels of every lattice once (untimed)
@@ -325,7 +326,7 @@ def serve(args):
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, exponential gaps mean {args.mean_gap * 1e3:.0f} ms (seed 20), "
                                f"lattices {names} uniform, nrhs 1..{args.max_rhs}, eps=0.6 links, "
-                               f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s=6 nMR=8, FGMRES-DR(30,12), tol 1e-10, "
+                               f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s={args.serve_cycles} nMR=8, FGMRES-DR(30,12), tol 1e-10, "
                                f"{args.slots} slots" + (", captured steps" if args.serve_graphs else ""),
                    "m_c_from": {n: mc[n][1] for n in names}},
         "makespan_s": round(makespan, 3),
@@ -432,6 +433,7 @@ def main():
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
     ap.add_argument("--max-rhs", type=int, default=4)
     ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--serve-cycles", type=int, default=6, help="serving: SAP cycles per application")
     ap.add_argument("--serve-graphs", action="store_true",
                     help="serving: replay captured Arnoldi steps (HIP graphs) in single-RHS requests")
     ap.add_argument("--sap-study", action="store_true",
