@@ -485,4 +485,64 @@ __device__ __forceinline__ void hop_sum_block_ahead(int l, XB&& xin_blk, UB&& u_
   }
 }
 
+// Full hopping sum (faces included) for compile-time BS^4 blocks: each hop's
+// neighbour spinor is read into registers first, from the block (xin_blk,
+// in-block sites) or from the neighbouring block (xin_halo, face sites), so
+// that the hop arithmetic runs once per hop for all lanes (a branch per
+// source around the whole hop would run it twice on the faces of x, y, z).
+// Links: u_at(block, mu, e, local site); the backward hop's link comes from
+// this block or from the neighbouring block per lane, loaded one hop ahead
+// as in hop_sum_block_ahead.
+template <typename T, typename SG, int BS, typename XB, typename XH, typename UA>
+__device__ __forceinline__ void hop_sum_halo_ahead(const Geom& g, int b, int l, const int bc[4], XB&& xin_blk,
+                                                   XH&& xin_halo, UA&& u_at, cplx<T> acc[12]) {
+  static_assert(BS > 0 && (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
+  constexpr int LB = ilog2(BS);
+  using W = decltype(u_at(0, 0, 0, 0));
+  auto dispatch = [&](int h, auto&& psi, auto&& u) {
+    if constexpr (is_link16<SG>) hop16_dispatch<SG>(h, acc, psi, u);
+    else hop_dispatch<T>(h, acc, psi, u);
+  };
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+  W wf[9], wb[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) wf[e] = u_at(b, 0, e, l);
+#pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    const int st = 1 << (LB * mu);
+    const int lcm = (l >> (LB * mu)) & (BS - 1);
+    // neighbouring blocks in +mu and -mu (uniform over the workgroup)
+    int cf[4] = {bc[0], bc[1], bc[2], bc[3]}, cb[4] = {bc[0], bc[1], bc[2], bc[3]};
+    cf[mu] = (bc[mu] + 1 == g.N[mu]) ? 0 : bc[mu] + 1;
+    cb[mu] = (bc[mu] == 0) ? g.N[mu] - 1 : bc[mu] - 1;
+    const int nbf = encode_block(g, cf), nbb = encode_block(g, cb);
+    const bool inf = lcm < BS - 1, inbk = lcm > 0;
+    const int nlb = inbk ? l - st : l + (BS - 1) * st;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) wb[e] = u_at(inbk ? b : nbb, mu, e, nlb);
+    cplx<T> q[12];
+    if (inf) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) q[k] = xin_blk(l + st, k);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) q[k] = xin_halo(nbf, l - (BS - 1) * st, k);
+    }
+    dispatch(2 * mu, [&](int k) { return q[k]; }, [&](int e) { return wf[e]; });
+    if (mu < 3) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) wf[e] = u_at(b, mu + 1, e, l);
+    }
+    if (inbk) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) q[k] = xin_blk(l - st, k);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) q[k] = xin_halo(nbb, nlb, k);
+    }
+    dispatch(2 * mu + 1, [&](int k) { return q[k]; }, [&](int e) { return wb[e]; });
+  }
+}
+
 }  // namespace dw

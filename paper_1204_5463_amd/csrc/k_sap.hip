@@ -153,9 +153,15 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
     __syncthreads();
     cplx<T> acc[12];
     if (active) {
-      hop_sum_staged<T, true, LK, BS>(
-          g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
-          [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); }, u_halo, acc);
+      if constexpr (BS > 0 && L16 && !CLOV)
+        hop_sum_halo_ahead<T, LK, BS>(
+            g, b, l, bc, [&](int nl, int k) { return rho_s[k * bvol + nl]; },
+            [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); },
+            [&](int nb, int mu, int e, int nl) { return u_halo(nb, mu, e, nl); }, acc);
+      else
+        hop_sum_staged<T, true, LK, BS>(
+            g, b, l, bc, lc, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk,
+            [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); }, u_halo, acc);
       if constexpr (CLOV) {
         // -1/2 hops + C z = -1/2 (hops - 2 C z)
         clover_acc_f<T>(Cl + (long long)b * kCloverPairs * bvol, bvol, l,
