@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
     __syncthreads();
     cplx<T> acc[12];
     if (active) {
-      if constexpr (BS > 0 && L16)
+      if constexpr (BS > 0 && std::is_same<T, float>::value)
         hop_sum_halo_ahead<T, LK, BS>(
             g, b, l, bc, [&](int nl, int k) { return rho_s[k * bvol + nl]; },
             [&](int nb, int nl, int k) { return ld<T>(zr + ((long long)nb * 12 + k) * bvol + nl); },
