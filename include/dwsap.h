@@ -187,6 +187,18 @@ int64_t dw_field_volume(dw_field field);
  * spinor arrays of nrhs * V * 12 complex128 each; they must not overlap. */
 dw_status dw_apply(dw_field field, double m0, const double* x, double* y, int32_t nrhs, hipStream_t stream);
 
+/* y = D x as dw_apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). It calls no allocator: the internal-layout copies of x and y
+ * use a fixed device array of dw_apply_noalloc_max_bytes() bytes (64 MiB)
+ * that each GPU holds from the first context created on it until the
+ * process ends. Every call on a GPU uses that GPU's one array, so calls
+ * that overlap on one GPU (different streams, or threads) race and must be
+ * serialised by the caller. Needs 2 * nrhs * V * 192 bytes (plus alignment):
+ * DW_EINVAL beyond the limit, before any GPU work. Asynchronous on `stream`. */
+dw_status dw_apply_noalloc(dw_field field, double m0, const double* x, double* y, int32_t nrhs, hipStream_t stream);
+size_t dw_apply_noalloc_max_bytes(void);
+
 /* Benchmark path: y = D x on buffers already in the library's internal
  * block-tiled layout at storage precision `prec` (complex pairs of that
  * precision, nrhs * V * 12 pairs each; size from dw_internal_bytes). The

@@ -189,6 +189,8 @@ def load(path: str = LIB_PATH):
         "dw_field_volume": (i64, [vp]),
         "dw_apply": (st, [vp, dbl, vp, vp, i32, vp]),
         "dw_apply_ex": (st, [vp, dbl, i32, vp, vp, i32, vp]),
+        "dw_apply_noalloc": (st, [vp, dbl, vp, vp, i32, vp]),
+        "dw_apply_noalloc_max_bytes": (ctypes.c_size_t, []),
         "dw_internal_bytes": (ctypes.c_size_t, [vp, i32, i32]),
         "dw_pack": (st, [vp, i32, vp, vp, i32, vp]),
         "dw_unpack": (st, [vp, i32, vp, vp, i32, vp]),
@@ -347,6 +349,13 @@ class Field:
             y = torch.empty_like(x)
         _check(lib().dw_apply(self.handle, float(m0), _dev_ptr(x), _dev_ptr(y), self._nrhs(x), _stream(stream)),
                "dw_apply")
+        return y
+
+    def apply_noalloc(self, m0: float, x: torch.Tensor, y: torch.Tensor, stream=None):
+        """y = D x through dw_apply_noalloc (no device allocation; the caller
+        provides y). Asynchronous on the stream."""
+        _check(lib().dw_apply_noalloc(self.handle, float(m0), _dev_ptr(x), _dev_ptr(y), self._nrhs(x),
+                                      _stream(stream)), "dw_apply_noalloc")
         return y
 
     def internal_bytes(self, prec, nrhs=1):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -51,6 +52,43 @@ using namespace dw;
 
 namespace {
 
+// Device memory of dw_apply_noalloc: the internal-layout copies of x and y
+// live in this file-scope array instead of allocated buffers. Each GPU the
+// library runs on holds its own copy until the process ends. In host code
+// the name stands for a host-side shadow, not a device address: host code
+// uses only the address that hipGetSymbolAddress returned for the device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up this device's copy of the scratch array once per device; the
+// device must be current.
+dw_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the scratch table holds", device, kMaxDevices);
+    return DW_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return DW_OK;
+  void* p = nullptr;
+  DW_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) {
+    set_error("hipGetSymbolAddress returned no address for the scratch array on device %d", device);
+    return DW_EHIP;
+  }
+  g_scratch_ptr[device] = p;
+  return DW_OK;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 dw_status check_device(dw_ctx ctx) {
   int cur = -1;
   DW_CHECK_HIP(hipGetDevice(&cur));
@@ -82,6 +120,7 @@ dw_status dw_ctx_create(int32_t device, const dw_allocator* alloc, dw_ctx* out) 
     return DW_EINVAL;
   }
   DW_CHECK_HIP(hipSetDevice(device));
+  DW_TRY(scratch_setup(device));
   dw_ctx c = new (std::nothrow) dw_ctx_s;
   if (!c) {
     set_error("out of host memory");
@@ -223,6 +262,43 @@ dw_status dw_apply(dw_field f, double m0, const double* x, double* y, int32_t nr
   DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, yi.p, y, 1.0, nrhs, stream));
   DW_CHECK_HIP(hipStreamSynchronize(stream));
   return DW_OK;
+}
+
+size_t dw_apply_noalloc_max_bytes(void) { return kScratchBytes; }
+
+dw_status dw_apply_noalloc(dw_field f, double m0, const double* x, double* y, int32_t nrhs, hipStream_t stream) {
+  clear_error();
+  if (!f || !x || !y || nrhs < 0) {
+    set_error("dw_apply_noalloc: invalid argument");
+    return DW_EINVAL;
+  }
+  if (nrhs == 0) return DW_OK;
+  if (x == y) {
+    set_error("dw_apply_noalloc: x and y must not overlap");
+    return DW_EINVAL;
+  }
+  const Geom& g = f->g;
+  const size_t one = (size_t)g.V * 12 * 16 * (size_t)nrhs;  // one internal FP64 copy
+  const size_t yofs = (one + 255) & ~(size_t)255;
+  if (yofs + one > kScratchBytes) {
+    set_error("dw_apply_noalloc: %d right-hand side(s) of %lld sites need %zu bytes of scratch, above its %zu bytes",
+              (int)nrhs, (long long)g.V, yofs + one, kScratchBytes);
+    return DW_EINVAL;
+  }
+  DW_TRY(check_device(f->ctx));
+  unsigned char* base = (unsigned char*)scratch_ptr(f->ctx->device);
+  if (!base) {
+    set_error("dw_apply_noalloc: no scratch address for device %d", f->ctx->device);
+    return DW_EHIP;
+  }
+  ProfScope ps(f->ctx);
+  const long long n = g.V * 12;
+  void* xi = base;
+  double* yi = (double*)(base + yofs);
+  DW_TRY(launch_pack_spinor(g, DW_PREC_F64, x, xi, 1.0, nrhs, stream));
+  DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, xi, 1.0, f->U[DW_PREC_F64], yi, nullptr, 0, nrhs, n, n, stream,
+                             nullptr, f->C[DW_PREC_F64]));
+  return launch_unpack_spinor(g, DW_PREC_F64, yi, y, 1.0, nrhs, stream);
 }
 
 dw_status dw_apply_ex(dw_field f, double m0, int32_t prec, const void* x, void* y, int32_t nrhs, hipStream_t stream) {
