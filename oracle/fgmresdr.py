@@ -1,8 +1,12 @@
 """Flexible GMRES with deflated restarts (FGMRES-DR), FP64 NumPy oracle.
 
 Test infrastructure only. Follows the paper's Section 4:
-  * flexible Arnoldi process (Alg. 3) with modified Gram-Schmidt as
-    written there, keeping the preconditioned vectors z_j = M_j v_j;
+  * flexible Arnoldi process (Alg. 3), keeping the preconditioned vectors
+    z_j = M_j v_j; the new vector A z_j is made orthogonal to v_1..v_j by
+    projection, repeated once (the listing orthogonalises one basis vector
+    at a time; in exact arithmetic every Gram-Schmidt variant yields the
+    same coefficients h_{i,j}, and the repeated projection keeps V
+    orthonormal to FP64 rounding);
   * flexible Arnoldi relation A Z_m = V_{m+1} H^_m and the small least
     squares problem for the iterate (Section 4.2);
   * harmonic Ritz pairs from H_m + f_m h_m^H with H_m^H f_m = h_m
@@ -91,20 +95,44 @@ def injected_vector(Vk, v_old, r):
     return v_old
 
 
+def project_out(Vj, w):
+    """Coefficients and remainder of w against the orthonormal columns of Vj.
+
+    Returns (h, w') with w = Vj h + w' and Vj^H w' = 0 (to rounding): the
+    projection h = Vj^H w, w' = w - Vj h is applied twice and the two
+    coefficient vectors are summed.
+    """
+    h = np.zeros(Vj.shape[1], dtype=np.complex128)
+    for _ in range(2):
+        g = Vj.conj().T @ w
+        w = w - Vj @ g
+        h = h + g
+    return h, w
+
+
+def arnoldi_step(A, M, V, Z, H, j):
+    """One flexible Arnoldi step (Alg. 3) on column j (0-based): the
+    preconditioned vector z_j = M_j v_j is kept, w = A z_j gives the new
+    Hessenberg column H[:j+1, j] by projection onto v_1..v_{j+1} and
+    h_{j+2,j+1} = ||w'|| (0-based H[j+1, j]). Returns the remainder w';
+    the caller normalises it into v_{j+2} unless the step broke down."""
+    Z[:, j] = M(V[:, j])
+    h, w = project_out(V[:, :j + 1], A(Z[:, j]))
+    H[:j + 1, j] = h
+    H[j + 1, j] = np.linalg.norm(w)
+    return w
+
+
 def flexible_arnoldi(A, M, b, m):
-    """Alg. 3: m steps from v_1 = b/||b||. Returns (V, Z, H)."""
+    """Alg. 3: m steps from v_1 = b/||b||. Returns (V, Z, H) with
+    A Z = V H (the flexible Arnoldi relation of Section 4.2)."""
     n = b.size
     V = np.zeros((n, m + 1), dtype=np.complex128)
     Z = np.zeros((n, m), dtype=np.complex128)
     H = np.zeros((m + 1, m), dtype=np.complex128)
     V[:, 0] = b / np.linalg.norm(b)
     for j in range(m):
-        Z[:, j] = M(V[:, j])
-        w = A(Z[:, j])
-        for i in range(j + 1):
-            H[i, j] = np.vdot(V[:, i], w)
-            w = w - H[i, j] * V[:, i]
-        H[j + 1, j] = np.linalg.norm(w)
+        w = arnoldi_step(A, M, V, Z, H, j)
         V[:, j + 1] = w / H[j + 1, j]
     return V, Z, H
 
@@ -154,13 +182,8 @@ def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
         broke = False
         # flexible Arnoldi steps j0 .. m-1 (0-based column index)
         for j in range(j0, m):
-            Z[:, j] = M(V[:, j])
-            w = A(Z[:, j])
+            w = arnoldi_step(A, M, V, Z, H, j)
             iters += 1
-            for i in range(j + 1):
-                H[i, j] = np.vdot(V[:, i], w)
-                w = w - H[i, j] * V[:, i]
-            H[j + 1, j] = np.linalg.norm(w)
             jend = j + 1
             hnorm = np.linalg.norm(H[:j + 2, :j + 1])
             broke = bool(abs(H[j + 1, j]) <= breakdown_tol * hnorm)

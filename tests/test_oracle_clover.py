@@ -100,3 +100,24 @@ def test_site_by_site_matches_whole_lattice():
     Cs = Cl.clover_at_sites(U, 1.4, sites)
     flat = C.reshape((V, 4, 3, 4, 3))
     assert np.max(np.abs(Cs - flat[sites])) < 1e-14
+
+
+def test_sampled_sites_with_clover_match_whole_lattice():
+    """apply_D_at_sites with the site-local term (used to sample D_sw on
+    lattices too large for a whole-field comparison) equals the whole-field
+    D_sw = D + C, at sites on every face and wrap of a 4x4x4x8 lattice."""
+    U = synth.gauge_field(L, 0.7, 2)
+    csw, m0 = 1.9, -0.31
+    C = Cl.clover_term(U, csw)
+    x = synth.gaussian_spinor(L, 1009)
+    y = W.apply_D(U, m0, x, C).reshape(-1, 4, 3)
+    V = int(np.prod(L))
+    rng = np.random.default_rng(5)
+    sites = np.unique(np.concatenate([[0, 3, 12, 15, 48, 63, V - 64, V - 1], rng.integers(0, V, 40)]))
+    Cs = Cl.clover_at_sites(U, csw, sites)
+    ys = W.apply_D_at_sites(U, m0, x, sites, Cs)
+    scale = np.max(np.abs(y))
+    assert np.max(np.abs(ys - y[sites])) <= 1e-14 * scale
+    # the clover part is really present in the sampled values
+    ys0 = W.apply_D_at_sites(U, m0, x, sites)
+    assert np.max(np.abs(ys0 - ys)) > 1e-2 * scale
