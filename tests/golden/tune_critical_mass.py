@@ -10,6 +10,7 @@ a near-critical mass is m0 = m_c + delta.
 
 Usage: python tests/golden/tune_critical_mass.py [name ...]
 """
+import fcntl
 import json
 import os
 import sys
@@ -28,7 +29,7 @@ from oracle import wilson as W  # noqa: E402
 
 OUT = os.path.join(HERE, "critical_mass.json")
 
-# name: (L, eps, gauge seed[, clover coefficient])
+# name: (L, eps, gauge seed[, clover coefficient[, ARPACK settings]])
 FIELDS = {
     "8^4_eps0.3": ((8, 8, 8, 8), 0.3, 0),
     "8^4_eps0.7": ((8, 8, 8, 8), 0.7, 0),
@@ -39,6 +40,12 @@ FIELDS = {
     "16^3x32_eps0.7": ((16, 16, 16, 32), 0.7, 0),
     "8^4_eps0.7_csw1.9": ((8, 8, 8, 8), 0.7, 0, 1.9),
     "12^4_eps0.7_csw1.9": ((12, 12, 12, 12), 0.7, 0, 1.9),
+    # 25.2M unknowns: fewer Ritz values and a looser tolerance keep the basis
+    # (ncv vectors of 403 MB) in host memory and the matvec count bounded;
+    # the critical mass is needed to about 1e-5
+    "32^3x64_eps0.7": ((32, 32, 32, 64), 0.7, 0, 0.0, dict(nev=4, ncv=24, tol=1e-7)),
+    "24^3x48_eps0.6": ((24, 24, 24, 48), 0.6, 0, 0.0, dict(nev=4, ncv=32, tol=1e-7)),
+    "32^3x64_eps0.6": ((32, 32, 32, 64), 0.6, 0, 0.0, dict(nev=4, ncv=24, tol=1e-7)),
 }
 
 
@@ -65,17 +72,26 @@ def main(names):
     for name in names:
         L, eps, seed = FIELDS[name][:3]
         csw = FIELDS[name][3] if len(FIELDS[name]) > 3 else 0.0
-        ev, nmv, secs = leftmost(L, eps, seed, csw)
+        opts = dict(nev=12, ncv=64, tol=1e-9)
+        opts.update(FIELDS[name][4] if len(FIELDS[name]) > 4 else {})
+        ev, nmv, secs = leftmost(L, eps, seed, csw, **opts)
+        # several runs may finish at once: read-modify-write under a lock
+        lock = open(OUT + ".lock", "w")
+        fcntl.flock(lock, fcntl.LOCK_EX)
         data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         data[name] = {
             "L": list(L), "eps": eps, "seed": seed, "csw": csw,
             "leftmost_eigenvalues_D0": [[float(e.real), float(e.imag)] for e in ev],
             "m_c": float(-ev[0].real),
             "matvecs": nmv, "seconds": round(secs, 1),
-            "method": "scipy.sparse.linalg.eigs(which='SR', k=12, ncv=64, tol=1e-9) on oracle.wilson.apply_D(U, 0, ., C) "
-                      "(C = oracle.clover.clover_term(U, csw) when csw != 0)",
+            "method": f"scipy.sparse.linalg.eigs(which='SR', k={opts['nev']}, ncv={opts['ncv']}, tol={opts['tol']:g}) "
+                      "on oracle.wilson.apply_D(U, 0, ., C) (C = oracle.clover.clover_term(U, csw) when csw != 0)",
         }
-        json.dump(data, open(OUT, "w"), indent=1)
+        with open(OUT + ".tmp", "w") as fh:
+            json.dump(data, fh, indent=1)
+        os.replace(OUT + ".tmp", OUT)
+        fcntl.flock(lock, fcntl.LOCK_UN)
+        lock.close()
         print(name, "m_c", -ev[0].real, "edge", ev[:4], nmv, "matvecs", round(secs), "s", flush=True)
 
 
