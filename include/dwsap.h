@@ -108,11 +108,16 @@ typedef struct sap_params {
  *              over span Z_k) and restarts with a fresh Krylov space, as in
  *              GMRES with projection; 0 = independent FGMRES-DR solves. Not
  *              in the paper; the projection cannot raise the residual.
- *   flags      DW_SOLVE_GRAPHS: capture each Arnoldi step (preconditioner,
- *              operator, Gram-Schmidt and small dense kernels) as a HIP graph
- *              the first time it runs and replay it in later cycles (fewer
- *              launches; used for single-RHS solves on a non-default stream
- *              with per-kernel timing off, else ignored).
+ *   flags      DW_SOLVE_GRAPHS: capture each restart cycle (its Arnoldi
+ *              steps with preconditioner, operator, Gram-Schmidt and small
+ *              dense kernels, the cycle end and the restart) as one HIP graph
+ *              the first time a cycle of that shape runs, and replay it; the
+ *              workspace and the graphs stay with the field, so later solves
+ *              with the same m, k, SAP parameters, flags and RHS count
+ *              (any mass, tolerance, max_iter, restart_t and b) replay them
+ *              too. dw_field_destroy, dw_field_set_clover or a solve with
+ *              other parameters frees them. Used on a non-default stream with
+ *              per-kernel timing off, else ignored.
  *              DW_SOLVE_V32: store the Krylov basis V in FP32 (the arithmetic
  *              stays FP64), which halves the Gram-Schmidt traffic; the
  *              Arnoldi relation then holds to FP32 accuracy and the explicit
@@ -184,7 +189,9 @@ dw_status dw_field_set_clover(dw_field field, double csw, hipStream_t stream);
 int64_t dw_field_volume(dw_field field);
 
 /* y = D x for nrhs right-hand sides, FP64 (eq. 1). x and y: canonical
- * spinor arrays of nrhs * V * 12 complex128 each; they must not overlap. */
+ * spinor arrays of nrhs * V * 12 complex128 each; they must not overlap.
+ * Asynchronous on `stream`: its temporaries come from the context's
+ * allocator and go back to it in stream order. */
 dw_status dw_apply(dw_field field, double m0, const double* x, double* y, int32_t nrhs, hipStream_t stream);
 
 /* y = D x as dw_apply, for callers that cannot allocate device memory
@@ -215,7 +222,10 @@ dw_status dw_unpack(dw_field field, int32_t prec, const void* x_int, double* x, 
  * D^l y^l = r^l (eq. 2) solved by `sap.nmr` minimal-residual steps in the
  * storage precision `sap.storage`. Blocks of colour 0 (even sum of block
  * coordinates, containing the origin) go first; the correction is added,
- * z^l += y^l. v and z: canonical spinor arrays (nrhs each), no overlap. */
+ * z^l += y^l. v and z: canonical spinor arrays (nrhs each), no overlap.
+ * Below FP64 storage each v is scaled to unit RMS entries before the cast
+ * (M(a v) = a M(v)), the factor formed on the device. Asynchronous on
+ * `stream`, temporaries as for dw_apply. */
 dw_status sap_precondition(dw_field field, double m0, const sap_params* sap, const double* v, double* z,
                            int32_t nrhs, hipStream_t stream);
 
@@ -243,11 +253,39 @@ dw_status sap_solve(dw_field field, double m0, const sap_params* sap, const doub
  * is computed in FP64 once per cycle and enters the least-squares right-hand
  * side (Section 4.7); the preconditioner runs at `params->sap.storage`.
  * b, x: canonical spinor arrays (nrhs each). stats: host array of nrhs
- * entries (may be NULL). Synchronises `stream` once per Arnoldi step (to
- * read the step's residual and breakdown scalars) and before returning. Returns DW_ENOTCONV if any RHS stopped at max_iter (x then
- * holds its last iterate and stats are filled). */
+ * entries (may be NULL). The stopping tests (implicit residual, breakdown,
+ * iteration limit within a cycle; explicit residual, clean or deflated
+ * restart at its end) are taken on the device, so the call synchronises
+ * `stream` once per restart cycle (to read each right-hand side's state)
+ * and before returning. Returns DW_ENOTCONV if any RHS stopped at max_iter
+ * (x then holds its last iterate and stats are filled). */
 dw_status fgmresdr_solve(dw_field field, double m0, const fgmresdr_params* params, const double* b, double* x,
                          int32_t nrhs, dw_solve_stats* stats, hipStream_t stream);
+
+/* ---- small dense steps, on host arrays ----------------------------------------
+ * The solver runs these one-wavefront FP64 kernels on its own device data;
+ * these entry points run the same kernels on host arrays (copied in and out,
+ * synchronous on the null stream, temporaries from the context's allocator)
+ * so that they can be compared with a reference. Complex numbers are
+ * interleaved (re, im) doubles; matrices are column-major.
+ *
+ * dw_dense_lsq: the least-squares problem of Section 4.2,
+ *   eta = argmin ||c - H^ eta||, H^ of (cols + 1) x cols (leading dimension
+ *   cols + 1), c of cols + 1 entries; eta receives cols entries, *resid the
+ *   residual norm ||c - H^ eta|| (by Householder QR). 1 <= cols <= 48.
+ * dw_dense_restart: the deflated restart of Alg. 4 (Lemma 1, Section 4.4)
+ *   for a cycle of mm columns: H^ of (mm + 1) x mm (leading dimension mm + 1),
+ *   c (mm + 1) and eta (mm). Outputs: ritz (mm entries) all harmonic Ritz
+ *   values, eigenvalues of H_m + f h_m^H with H_m^H f = h_m, sorted by
+ *   modulus (stable); Q ((mm + 1) x (k + 1), leading dimension mm + 1) the
+ *   orthonormal factor of G_{k+1} = [[G_k; 0], c - H^ eta], G_k holding the
+ *   unit eigenvectors of the k smallest; Hk ((k + 1) x k, leading dimension
+ *   k + 1) = Q^H H^ Q_k. *status: 0 ok, 1 singular H_m, 2 eigenvalue
+ *   iteration failed, 3 non-finite value (outputs then undefined).
+ *   2 <= mm <= 48, 1 <= k < mm, k <= 23. */
+dw_status dw_dense_lsq(dw_ctx ctx, int32_t cols, const double* Hhat, const double* c, double* eta, double* resid);
+dw_status dw_dense_restart(dw_ctx ctx, int32_t mm, int32_t k, const double* Hhat, const double* c, const double* eta,
+                           double* ritz, double* Q, double* Hk, int32_t* status);
 
 /* ---- serving loop ----------------------------------------------------------
  * A server solves requests of different lattices, masses and RHS counts

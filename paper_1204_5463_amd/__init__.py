@@ -143,7 +143,7 @@ class SolverParams:
     restart_t: float = 5.0
     sap: SapParams = dataclasses.field(default_factory=SapParams)
     shared_defl: int = 0
-    # SOLVE_GRAPHS: replay captured steps (single RHS, non-default stream); SOLVE_V32: FP32 basis;
+    # SOLVE_GRAPHS: replay captured restart cycles, kept with the field (non-default stream); SOLVE_V32: FP32 basis;
     # SOLVE_INJECT: explicit residual also in G_{k+1} and v_{k+1} at deflated restarts (Section 4.7)
     flags: int = 0
 
@@ -191,6 +191,8 @@ def load(path: str = LIB_PATH):
         "dw_apply_ex": (st, [vp, dbl, i32, vp, vp, i32, vp]),
         "dw_apply_noalloc": (st, [vp, dbl, vp, vp, i32, vp]),
         "dw_apply_noalloc_max_bytes": (ctypes.c_size_t, []),
+        "dw_dense_lsq": (st, [vp, i32, vp, vp, vp, ctypes.POINTER(dbl)]),
+        "dw_dense_restart": (st, [vp, i32, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]),
         "dw_internal_bytes": (ctypes.c_size_t, [vp, i32, i32]),
         "dw_pack": (st, [vp, i32, vp, vp, i32, vp]),
         "dw_unpack": (st, [vp, i32, vp, vp, i32, vp]),
@@ -344,7 +346,7 @@ class Field:
         return n
 
     def apply(self, m0: float, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
-        """y = D x (eq. 1), FP64. Synchronous."""
+        """y = D x (eq. 1), FP64. Asynchronous on the stream."""
         if y is None:
             y = torch.empty_like(x)
         _check(lib().dw_apply(self.handle, float(m0), _dev_ptr(x), _dev_ptr(y), self._nrhs(x), _stream(stream)),
@@ -381,7 +383,7 @@ class Field:
                                  int(nrhs), _stream(stream)), "dw_apply_ex")
 
     def sap(self, m0: float, params: SapParams, v: torch.Tensor, z: torch.Tensor | None = None, stream=None):
-        """z = M v: SAP (Alg. 2) with MR block solves. Synchronous."""
+        """z = M v: SAP (Alg. 2) with MR block solves. Asynchronous on the stream."""
         if z is None:
             z = torch.empty_like(v)
         p = params._c()
@@ -623,6 +625,47 @@ def autotune(ctx: Context, L, U: torch.Tensor, m0: float, base: SolverParams, b:
     if cache is not None:
         cache.put(key, bestp, trials)
     return bestp, trials
+
+
+def _host_c128(a):
+    import numpy as np
+    return np.asfortranarray(np.asarray(a, dtype=np.complex128))
+
+
+def dense_lsq(ctx: Context, Hhat, c):
+    """eta = argmin ||c - H^ eta|| by the solver's small dense kernel (Section 4.2).
+    Hhat: (cols + 1) x cols, c: cols + 1 (host arrays). Returns (eta, residual norm)."""
+    import numpy as np
+    H = _host_c128(Hhat)
+    cols = H.shape[1]
+    if H.shape[0] != cols + 1:
+        raise ValueError("H^ must have one more row than columns")
+    cv = np.ascontiguousarray(np.asarray(c, dtype=np.complex128).reshape(-1))
+    eta = np.zeros(cols, dtype=np.complex128)
+    res = ctypes.c_double()
+    _check(lib().dw_dense_lsq(ctx.handle, int(cols), H.ctypes.data, cv.ctypes.data, eta.ctypes.data,
+                              ctypes.byref(res)), "dw_dense_lsq")
+    return eta, res.value
+
+
+def dense_restart(ctx: Context, Hhat, c, eta, k: int):
+    """The deflated-restart step (Lemma 1, Section 4.4) by the solver's small dense kernel.
+    Returns (harmonic Ritz values sorted by modulus, Q_{k+1}, H^_k, status)."""
+    import numpy as np
+    H = _host_c128(Hhat)
+    mm = H.shape[1]
+    if H.shape[0] != mm + 1:
+        raise ValueError("H^ must have one more row than columns")
+    cv = np.ascontiguousarray(np.asarray(c, dtype=np.complex128).reshape(-1))
+    ev = np.ascontiguousarray(np.asarray(eta, dtype=np.complex128).reshape(-1))
+    ritz = np.zeros(mm, dtype=np.complex128)
+    Q = np.zeros((mm + 1, k + 1), dtype=np.complex128, order="F")
+    Hk = np.zeros((k + 1, k), dtype=np.complex128, order="F")
+    status = ctypes.c_int32()
+    _check(lib().dw_dense_restart(ctx.handle, int(mm), int(k), H.ctypes.data, cv.ctypes.data, ev.ctypes.data,
+                                  ritz.ctypes.data, Q.ctypes.data, Hk.ctypes.data, ctypes.byref(status)),
+           "dw_dense_restart")
+    return ritz, np.asarray(Q), np.asarray(Hk), int(status.value)
 
 
 def to_device(a, device="cuda"):

@@ -41,6 +41,9 @@ struct dw_field_s {
   void* C[4];  // clover term per dw_prec (null without one)
   double csw;
   hipStream_t stream;  // stream the field was created on (its memory is freed there)
+  // solver workspace and captured cycles kept for the next solve (DW_SOLVE_GRAPHS)
+  void* solver_cache = nullptr;
+  void (*solver_cache_free)(void*) = nullptr;
 };
 
 namespace dw {
@@ -132,10 +135,11 @@ inline size_t pair_bytes(int prec) { return prec == DW_PREC_F64 ? 16 : prec == D
 
 // ---- launchers (kernels in the .hip files) --------------------------------------
 // All counts in complex pairs; nrhs fields are stacked with stride V*12 pairs.
+// dscale (may be null): a device factor per right-hand side r at dscale[r * dstride], multiplying scale
 dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* out, double scale, int nrhs,
-                             hipStream_t s);
+                             hipStream_t s, const double* dscale = nullptr, int dstride = 0);
 dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* out, double scale, int nrhs,
-                               hipStream_t s);
+                               hipStream_t s, const double* dscale = nullptr, int dstride = 0);
 dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out, hipStream_t s);
 // sigma_{mu nu} chirality blocks (2x2) for the six planes mu < nu
 struct SigmaBlocks {
@@ -147,25 +151,30 @@ dw_status launch_clover_build(const Geom& g, const void* U64, double csw, double
 // elementwise out = scale * (dscale ? dscale[0] : 1) * in over n pairs
 // (precision conversion; dscale is a device scalar)
 dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s,
-                         const double* dscale = nullptr);
+                         const double* dscale = nullptr, const int* gate = nullptr);
 
 // y = scale * D x (mode 0) or y = b - scale * D x (mode 1), internal layout.
 // prec_x: DW_PREC_F64 or DW_PREC_F32 input with FP64 links/output/arithmetic
 // when outer = true; otherwise everything at precision prec_x (FP32 math).
 // rlist (device, may be null): the nrhs right-hand-side indices to process.
+// gate (device, may be null): right-hand side r is skipped when gate[r * gstride] == 0.
+// dmass (device, may be null): the mass is read there instead of m0.
 dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
                               double* y, const double* b, int mode, int nrhs, long long x_rhs_stride,
                               long long y_rhs_stride, hipStream_t s, const int* rlist = nullptr,
-                              const void* C64 = nullptr);
+                              const void* C64 = nullptr, const int* gate = nullptr, int gstride = 0,
+                              const double* dmass = nullptr);
 dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
                              hipStream_t s, const void* C = nullptr);
 
 // One SAP colour sweep: for every block of `colour`, r = v - D z on the
 // block, nmr MR steps on D^l y = r, z += y. v at storage precision `prec`,
 // z at FP64 (prec F64) or FP32 (otherwise). z_zero: z is zero on entry.
+// gate, dmass as for launch_dslash_outer.
 dw_status launch_sap_colour(const Geom& g, double m0, int prec, const void* v, void* z, const void* U, int colour,
                             int nmr, int z_zero, int nrhs, long long v_rhs_stride, long long z_rhs_stride,
                             hipStream_t s, const int* rlist = nullptr, const void* C = nullptr,
-                            double mr_reduction = 0.0);
+                            double mr_reduction = 0.0, const int* gate = nullptr, int gstride = 0,
+                            const double* dmass = nullptr);
 
 }  // namespace dw

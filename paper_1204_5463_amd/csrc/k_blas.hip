@@ -35,7 +35,14 @@ __device__ __forceinline__ double wsum(double a) {
 template <typename SV>
 __global__ void __launch_bounds__(kThreads)
     k_dots(const SV* __restrict__ V, long long stride, int ncols, const s64* __restrict__ w, long long n,
-           s64* __restrict__ partials) {
+           s64* __restrict__ partials, const int* __restrict__ gate, const int* __restrict__ dn, int dadd, int c0) {
+  if (gate && *gate == 0) return;
+  if (dn) {
+    // columns c0.. of a device-side count
+    const int left = *dn + dadd - c0;
+    if (left <= 0) return;
+    ncols = left < kDotCols ? left : kDotCols;
+  }
   __shared__ double red[kThreads / kWave][kDotCols][2];
   cplx<double> acc[kDotCols];
 #pragma unroll
@@ -70,7 +77,10 @@ __global__ void __launch_bounds__(kThreads)
 
 // out[c*ostride] (op 0: =, op 1: +=) sum_g partials[c*G + g]; one wave per column
 __global__ void __launch_bounds__(kThreads)
-    k_reduce(const s64* __restrict__ partials, int G, int ncols, s64* __restrict__ out, int ostride, int op) {
+    k_reduce(const s64* __restrict__ partials, int G, int ncols, s64* __restrict__ out, int ostride, int op,
+             const int* __restrict__ gate, const int* __restrict__ dn, int dmul, int dadd) {
+  if (gate && *gate == 0) return;
+  if (dn) ncols = dmul * *dn + dadd;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   for (int c = wave; c < ncols; c += kThreads / kWave) {
     double re = 0, im = 0;
@@ -110,14 +120,18 @@ __global__ void __launch_bounds__(kThreads)
 // y = x * (alpha[0] if alpha_is_inv == 0 else 1/alpha[0]) with alpha a device
 // scalar stored as the real part of a complex pair
 __global__ void __launch_bounds__(kThreads)
-    k_scale(const s64* __restrict__ x, s64* __restrict__ y, const double* __restrict__ alpha, long long n) {
+    k_scale(const s64* __restrict__ x, s64* __restrict__ y, const double* __restrict__ alpha, long long n,
+            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const double a = alpha[0];
   const long long step = (long long)gridDim.x * kThreads;
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) st(y + i, a * ld<double>(x + i));
 }
 
 // x *= alpha (complex, device)
-__global__ void __launch_bounds__(kThreads) k_scale_c(s64* __restrict__ x, const s64* __restrict__ alpha, long long n) {
+__global__ void __launch_bounds__(kThreads)
+    k_scale_c(s64* __restrict__ x, const s64* __restrict__ alpha, long long n, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const cplx<double> a = ld<double>(alpha);
   const long long step = (long long)gridDim.x * kThreads;
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) st(x + i, a * ld<double>(x + i));
@@ -127,7 +141,9 @@ __global__ void __launch_bounds__(kThreads) k_scale_c(s64* __restrict__ x, const
 template <typename SZ>
 __global__ void __launch_bounds__(kThreads)
     k_combine(const SZ* __restrict__ Z, long long stride, int ncols, const s64* __restrict__ coef, double scale,
-              s64* __restrict__ x, long long n) {
+              s64* __restrict__ x, long long n, const int* __restrict__ gate, const int* __restrict__ dn) {
+  if (gate && *gate == 0) return;
+  if (dn) ncols = *dn < ncols ? *dn : ncols;
   __shared__ cplx<double> cs[64];
   for (int c = threadIdx.x; c < ncols; c += kThreads) cs[c] = scale * ld<double>(coef + c);
   __syncthreads();
@@ -143,7 +159,10 @@ __global__ void __launch_bounds__(kThreads)
 // Each thread reads all nin inputs of its element before writing any output.
 template <typename SV>
 __global__ void __launch_bounds__(kThreads)
-    k_rotate(SV* __restrict__ V, long long stride, int nin, const s64* __restrict__ Q, int ldq, int nout, long long n) {
+    k_rotate(SV* __restrict__ V, long long stride, int nin, const s64* __restrict__ Q, int ldq, int nout, long long n,
+             const int* __restrict__ gate, const int* __restrict__ dn, int dadd) {
+  if (gate && *gate == 0) return;
+  if (dn) nin = *dn + dadd < nin ? *dn + dadd : nin;
   __shared__ cplx<double> qs[49 * kRotMax];
   for (int t = threadIdx.x; t < nin * nout; t += kThreads) {
     const int i = t % nin, c = t / nin;
@@ -178,8 +197,22 @@ __global__ void __launch_bounds__(kThreads)
 template <bool HU, bool HW, typename SV>
 __global__ void __launch_bounds__(kThreads)
     k_gs_reduce(const SV* __restrict__ V, long long stride, int c0, int nc, int nv, const SV* __restrict__ u,
-                const s64* __restrict__ w, long long n, int first, s64* __restrict__ partials) {
+                const s64* __restrict__ w, long long n, int first, s64* __restrict__ partials,
+                const int* __restrict__ gate, const int* __restrict__ dcol, int chunk) {
   constexpr int NA = kGsCols;
+  if (gate && *gate == 0) return;
+  if (dcol) {
+    // finalising column nv = *dcol against the nv columns before it: the
+    // chunk split of the host-side form, on the device-side count
+    nv = *dcol;
+    u = V + (long long)nv * stride;
+    const int nchunks = nv > 0 ? (nv + NA - 1) / NA : 1;
+    if (chunk >= nchunks) return;
+    const int per = nv > 0 ? (nv + nchunks - 1) / nchunks : 0;
+    c0 = chunk * per;
+    nc = nv - c0 < per ? nv - c0 : per;
+    first = chunk == 0;
+  }
   __shared__ double red[kThreads / kWave][2 * NA + 3][2];
   cplx<double> au[NA], aw[NA], uu = mk(0.0, 0.0), uw = mk(0.0, 0.0), ww = mk(0.0, 0.0);
 #pragma unroll
@@ -250,7 +283,10 @@ __global__ void __launch_bounds__(kThreads)
 template <bool HU, bool HW, typename SV>
 __global__ void __launch_bounds__(kThreads)
     k_gs_update(SV* __restrict__ V, long long stride, int nv, int jcol, const s64* __restrict__ w,
-                SV* __restrict__ wout, const s64* __restrict__ coef, long long n, s64* __restrict__ partials) {
+                SV* __restrict__ wout, const s64* __restrict__ coef, long long n, s64* __restrict__ partials,
+                const int* __restrict__ gate, const int* __restrict__ dcol) {
+  if (gate && *gate == 0) return;
+  if (dcol) nv = jcol = *dcol;
   __shared__ cplx<double> ca[kMaxM + 1], cb[kMaxM + 1];
   __shared__ double red[kThreads / kWave];
   for (int c = threadIdx.x; c < nv; c += kThreads) {
@@ -317,21 +353,25 @@ unsigned grid_for(long long n) {
 }  // namespace
 
 dw_status blas_dots(int prec_v, const void* V, long long stride, int ncols, const double* w, long long n,
-                    double* partials, double* out, int ostride, int op, hipStream_t s) {
+                    double* partials, double* out, int ostride, int op, hipStream_t s, const int* gate, const int* dn,
+                    int dadd) {
   const unsigned G = grid_for(n);
   for (int c0 = 0; c0 < ncols; c0 += kDotCols) {
     const int nc = ncols - c0 < kDotCols ? ncols - c0 : kDotCols;
     s64* part = (s64*)partials + (long long)c0 * G;
     KTimer kt(DW_K_DOTS, s);
     if (prec_v == DW_PREC_F64)
-      hipLaunchKernelGGL(k_dots<s64>, G, kThreads, 0, s, (const s64*)V + c0 * stride, stride, nc, (const s64*)w, n, part);
+      hipLaunchKernelGGL(k_dots<s64>, G, kThreads, 0, s, (const s64*)V + c0 * stride, stride, nc, (const s64*)w, n,
+                         part, gate, dn, dadd, c0);
     else
-      hipLaunchKernelGGL(k_dots<s32>, G, kThreads, 0, s, (const s32*)V + c0 * stride, stride, nc, (const s64*)w, n, part);
+      hipLaunchKernelGGL(k_dots<s32>, G, kThreads, 0, s, (const s32*)V + c0 * stride, stride, nc, (const s64*)w, n,
+                         part, gate, dn, dadd, c0);
     DW_CHECK_LAUNCH();
     kt.done((double)n * (nc * (double)pair_bytes(prec_v) + 16), (double)n * nc * 8);
   }
   KTimer kr(DW_K_REDUCE, s);
-  hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, ncols, (s64*)out, ostride, op);
+  hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, ncols, (s64*)out, ostride, op, gate,
+                     dn, 1, dadd);
   DW_CHECK_LAUNCH();
   kr.done((double)G * ncols * 16, (double)G * ncols * 2);
   return DW_OK;
@@ -350,49 +390,49 @@ dw_status blas_sub_cols(const double* V, long long stride, int ncols, const doub
   return DW_OK;
 }
 
-dw_status blas_scale(const double* x, double* y, const double* alpha, long long n, hipStream_t s) {
+dw_status blas_scale(const double* x, double* y, const double* alpha, long long n, hipStream_t s, const int* gate) {
   KTimer kt(DW_K_SCALE, s);
-  hipLaunchKernelGGL(k_scale, grid_for(n), kThreads, 0, s, (const s64*)x, (s64*)y, alpha, n);
+  hipLaunchKernelGGL(k_scale, grid_for(n), kThreads, 0, s, (const s64*)x, (s64*)y, alpha, n, gate);
   DW_CHECK_LAUNCH();
   kt.done((double)n * 32, (double)n * 2);
   return DW_OK;
 }
 
-dw_status blas_scale_c(double* x, const double* alpha, long long n, hipStream_t s) {
+dw_status blas_scale_c(double* x, const double* alpha, long long n, hipStream_t s, const int* gate) {
   KTimer kt(DW_K_SCALE, s);
-  hipLaunchKernelGGL(k_scale_c, grid_for(n), kThreads, 0, s, (s64*)x, (const s64*)alpha, n);
+  hipLaunchKernelGGL(k_scale_c, grid_for(n), kThreads, 0, s, (s64*)x, (const s64*)alpha, n, gate);
   DW_CHECK_LAUNCH();
   kt.done((double)n * 32, (double)n * 6);
   return DW_OK;
 }
 
 dw_status blas_combine(int prec_z, const void* Z, long long stride, int ncols, const double* coef, double scale,
-                       double* x, long long n, hipStream_t s) {
+                       double* x, long long n, hipStream_t s, const int* gate, const int* dn) {
   if (ncols > 64) {
     set_error("blas_combine: too many columns");
     return DW_EINVAL;
   }
   KTimer kt(DW_K_COMBINE, s);
   if (prec_z == DW_PREC_F64)
-    hipLaunchKernelGGL(k_combine<s64>, grid_for(n), kThreads, 0, s, (const s64*)Z, stride, ncols, (const s64*)coef, scale, (s64*)x, n);
+    hipLaunchKernelGGL(k_combine<s64>, grid_for(n), kThreads, 0, s, (const s64*)Z, stride, ncols, (const s64*)coef, scale, (s64*)x, n, gate, dn);
   else
-    hipLaunchKernelGGL(k_combine<s32>, grid_for(n), kThreads, 0, s, (const s32*)Z, stride, ncols, (const s64*)coef, scale, (s64*)x, n);
+    hipLaunchKernelGGL(k_combine<s32>, grid_for(n), kThreads, 0, s, (const s32*)Z, stride, ncols, (const s64*)coef, scale, (s64*)x, n, gate, dn);
   DW_CHECK_LAUNCH();
   kt.done((double)n * (ncols * (double)pair_bytes(prec_z) + 32), (double)n * ncols * 8);
   return DW_OK;
 }
 
 dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const double* Q, int ldq, int nout, long long n,
-                      hipStream_t s) {
+                      hipStream_t s, const int* gate, const int* dn, int dadd) {
   if (nin > 49 || nout > kRotMax || nout > nin) {
     set_error("blas_rotate: unsupported shape %d -> %d", nin, nout);
     return DW_EINVAL;
   }
   KTimer kt(DW_K_ROTATE, s);
   if (prec_v == DW_PREC_F64)
-    hipLaunchKernelGGL(k_rotate<s64>, grid_for(n), kThreads, 0, s, (s64*)V, stride, nin, (const s64*)Q, ldq, nout, n);
+    hipLaunchKernelGGL(k_rotate<s64>, grid_for(n), kThreads, 0, s, (s64*)V, stride, nin, (const s64*)Q, ldq, nout, n, gate, dn, dadd);
   else
-    hipLaunchKernelGGL(k_rotate<s32>, grid_for(n), kThreads, 0, s, (s32*)V, stride, nin, (const s64*)Q, ldq, nout, n);
+    hipLaunchKernelGGL(k_rotate<s32>, grid_for(n), kThreads, 0, s, (s32*)V, stride, nin, (const s64*)Q, ldq, nout, n, gate, dn, dadd);
   DW_CHECK_LAUNCH();
   kt.done((double)n * (nin + nout) * pair_bytes(prec_v), (double)n * nin * nout * 8);
   return DW_OK;
@@ -404,11 +444,12 @@ namespace dw {
 
 template <typename SV>
 dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, const s64* wp, long long n,
-                      double* partials, double* out, hipStream_t s) {
-  const bool hu = up != nullptr, hw = wp != nullptr;
+                      double* partials, double* out, hipStream_t s, const int* gate, const int* dcol) {
+  const bool hu = up != nullptr || dcol != nullptr, hw = wp != nullptr;
   const unsigned G = grid_for(n);
   // the columns in as few passes as possible, split evenly (u and w are
-  // re-read by every pass)
+  // re-read by every pass); with dcol the device picks the split of its
+  // count and nv bounds it
   const int nchunks = nv > 0 ? (nv + kGsCols - 1) / kGsCols : 1;
   const int per = nv > 0 ? (nv + nchunks - 1) / nchunks : 0;
   for (int q = 0; q < nchunks; ++q) {
@@ -418,56 +459,58 @@ dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, cons
     s64* part = (s64*)partials;
     if (hu && hw)
       hipLaunchKernelGGL((k_gs_reduce<true, true, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0,
-                         part);
+                         part, gate, dcol, q);
     else if (hu)
       hipLaunchKernelGGL((k_gs_reduce<true, false, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
-                         q == 0, part);
+                         q == 0, part, gate, dcol, q);
     else
       hipLaunchKernelGGL((k_gs_reduce<false, true, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
-                         q == 0, part);
+                         q == 0, part, gate, dcol, q);
     DW_CHECK_LAUNCH();
     kt.done((double)n * (sizeof(SV) * (nc + (hu ? 1 : 0)) + (hw ? 16 : 0)),
             (double)n * 8 * nc * ((hu ? 1 : 0) + (hw ? 1 : 0)));
   }
   KTimer kr(DW_K_REDUCE, s);
-  hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 2 * nv + 3, (s64*)out, 1, 0);
+  hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 2 * nv + 3, (s64*)out, 1, 0, gate,
+                     dcol, 2, 3);
   DW_CHECK_LAUNCH();
   kr.done((double)G * (2 * nv + 3) * 16, 0);
   return DW_OK;
 }
 
 dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const double* w, long long n,
-                    double* partials, double* out, hipStream_t s) {
-  if (nv < 0 || nv > kMaxM + 1 || (!u && !w) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
+                    double* partials, double* out, hipStream_t s, const int* gate, const int* dcol) {
+  if (nv < 0 || nv > kMaxM + 1 || (!u && !w && !dcol) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
     set_error("gs_reduce: bad arguments");
     return DW_EINVAL;
   }
   if (prec_v == DW_PREC_F64)
-    return gs_reduce_t((const s64*)V, stride, nv, (const s64*)u, (const s64*)w, n, partials, out, s);
-  return gs_reduce_t((const s32*)V, stride, nv, (const s32*)u, (const s64*)w, n, partials, out, s);
+    return gs_reduce_t((const s64*)V, stride, nv, (const s64*)u, (const s64*)w, n, partials, out, s, gate, dcol);
+  return gs_reduce_t((const s32*)V, stride, nv, (const s32*)u, (const s64*)w, n, partials, out, s, gate, dcol);
 }
 
 template <typename SV>
 dw_status gs_update_t(SV* Vp, long long stride, int nv, int jcol, const s64* w, SV* wout, const double* coef,
-                      long long n, double* partials, double* nrm2, hipStream_t s) {
-  const bool hu = jcol >= 0, hw = w != nullptr;
+                      long long n, double* partials, double* nrm2, hipStream_t s, const int* gate, const int* dcol) {
+  const bool hu = jcol >= 0 || dcol != nullptr, hw = w != nullptr;
   const unsigned G = grid_for(n);
   KTimer kt(DW_K_SUBCOLS, s);
   if (hu && hw)
     hipLaunchKernelGGL((k_gs_update<true, true, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
-                       (const s64*)coef, n, (s64*)partials);
+                       (const s64*)coef, n, (s64*)partials, gate, dcol);
   else if (hu)
     hipLaunchKernelGGL((k_gs_update<true, false, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
-                       (const s64*)coef, n, (s64*)partials);
+                       (const s64*)coef, n, (s64*)partials, gate, dcol);
   else
     hipLaunchKernelGGL((k_gs_update<false, true, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
-                       (const s64*)coef, n, (s64*)partials);
+                       (const s64*)coef, n, (s64*)partials, gate, dcol);
   DW_CHECK_LAUNCH();
   kt.done((double)n * (sizeof(SV) * (nv + (hu ? 2 : 0) + (hw ? 1 : 0)) + (hw ? 16 : 0)),
           (double)n * 8 * nv * ((hu ? 1 : 0) + (hw ? 1 : 0)));
   if (hw) {
     KTimer kr(DW_K_REDUCE, s);
-    hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 1, (s64*)nrm2, 1, 0);
+    hipLaunchKernelGGL(k_reduce, 1, kThreads, 0, s, (const s64*)partials, (int)G, 1, (s64*)nrm2, 1, 0, gate,
+                       (const int*)nullptr, 0, 0);
     DW_CHECK_LAUNCH();
     kr.done((double)G * 16, 0);
   }
@@ -475,14 +518,15 @@ dw_status gs_update_t(SV* Vp, long long stride, int nv, int jcol, const s64* w, 
 }
 
 dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const double* w, void* wout,
-                    const double* coef, long long n, double* partials, double* nrm2, hipStream_t s) {
-  if (nv < 0 || nv > kMaxM + 1 || (jcol < 0 && !w) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
+                    const double* coef, long long n, double* partials, double* nrm2, hipStream_t s, const int* gate,
+                    const int* dcol) {
+  if (nv < 0 || nv > kMaxM + 1 || (jcol < 0 && !w && !dcol) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
     set_error("gs_update: bad arguments");
     return DW_EINVAL;
   }
   if (prec_v == DW_PREC_F64)
-    return gs_update_t((s64*)V, stride, nv, jcol, (const s64*)w, (s64*)wout, coef, n, partials, nrm2, s);
-  return gs_update_t((s32*)V, stride, nv, jcol, (const s64*)w, (s32*)wout, coef, n, partials, nrm2, s);
+    return gs_update_t((s64*)V, stride, nv, jcol, (const s64*)w, (s64*)wout, coef, n, partials, nrm2, s, gate, dcol);
+  return gs_update_t((s32*)V, stride, nv, jcol, (const s64*)w, (s32*)wout, coef, n, partials, nrm2, s, gate, dcol);
 }
 
 }  // namespace dw

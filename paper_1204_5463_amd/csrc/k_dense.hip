@@ -17,6 +17,7 @@
 // Lanes work on rows or columns in parallel; serial steps (pivots, shifts,
 // rotations) are computed redundantly by every lane from the same LDS data,
 // so control flow is uniform across the wave.
+#include "dw_control.hpp"
 #include "dw_kernels.hpp"
 #include "dw_types.hpp"
 
@@ -147,7 +148,10 @@ __global__ void __launch_bounds__(kL) k_step(double* H, int j, const double* h1,
 // Coefficients of a delayed-reorthogonalisation Gram-Schmidt step (see
 // dense_gs_coef in dw_kernels.hpp). red: reduced slots of gs_reduce.
 __global__ void __launch_bounds__(kL) k_gs_coef(double* H, int nv, int jcol, int jw, int hu, int hw,
-                                                const double* red, double* coef, double* scal) {
+                                                const double* red, double* coef, double* scal, const int* gate,
+                                                const int* dcol) {
+  if (gate && *gate == 0) return;
+  if (dcol) nv = jcol = *dcol;
   const int lane = threadIdx.x;
   C a2sum{0, 0};
   double a2 = 0;
@@ -191,7 +195,8 @@ __global__ void __launch_bounds__(kL) k_gs_coef(double* H, int nv, int jcol, int
 }
 
 __global__ void __launch_bounds__(kL) k_step2(double* H, int j, const double* nrm2, const double* c, double* scal,
-                                              double bd_tol) {
+                                              double bd_tol, int* ctl, const double* ctld) {
+  if (ctl && ctl[kCLive] == 0) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   StepSmem& S = *reinterpret_cast<StepSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -213,14 +218,23 @@ __global__ void __launch_bounds__(kL) k_step2(double* H, int j, const double* nr
   const bool broke = !(hn > bd_tol * hnorm);
   hh_qr(S.A, kLd, rows, cols, S.rhs, S.Uv, kLd, S.beta);
   if (lane == 0) {
+    const double ri = cabs(S.rhs[rows - 1]);
     scal[kSclHnext] = hn;
     scal[kSclHinv] = broke ? 0.0 : 1.0 / hn;
-    scal[kSclResImp] = cabs(S.rhs[rows - 1]);
+    scal[kSclResImp] = ri;
     scal[kSclBreak] = broke ? 1.0 : 0.0;
+    if (ctl) {
+      ctl[kCJend] = j + 1;
+      ctl[kCBroke] = broke ? 1 : 0;
+      if (broke || ri <= ctld[kDTolAbs] || j + 1 >= ctl[kCJlim]) ctl[kCLive] = 0;
+    }
   }
 }
 
-__global__ void __launch_bounds__(kL) k_lsq(const double* H, int cols, const double* c, double* eta, double* scal) {
+__global__ void __launch_bounds__(kL) k_lsq(const double* H, int cols, const double* c, double* eta, double* scal,
+                                            const int* gate, const int* dn) {
+  if (gate && *gate == 0) return;
+  if (dn) cols = *dn;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   StepSmem& S = *reinterpret_cast<StepSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -239,7 +253,9 @@ __global__ void __launch_bounds__(kL) k_lsq(const double* H, int cols, const dou
 
 // Projection onto a deflation space (D Z_k = V_{k+1} H_k): y = argmin ||t - H_k y||
 // and s = H_k y, with H_k the (k+1) x k leading block of H.
-__global__ void __launch_bounds__(kL) k_project(const double* H, int k, const double* t, double* y, double* sv) {
+__global__ void __launch_bounds__(kL) k_project(const double* H, int k, const double* t, double* y, double* sv,
+                                                const int* gate) {
+  if (gate && *gate == 0) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   StepSmem& S = *reinterpret_cast<StepSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -266,7 +282,9 @@ __global__ void __launch_bounds__(kL) k_project(const double* H, int k, const do
   }
 }
 
-__global__ void __launch_bounds__(kL) k_fresh(double* H, double* c, const double* nrm2, double* scal) {
+__global__ void __launch_bounds__(kL) k_fresh(double* H, double* c, const double* nrm2, double* scal,
+                                              const int* gate) {
+  if (gate && *gate == 0) return;
   const int lane = threadIdx.x;
   const double beta = sqrt(fmax(nrm2[0], 0.0));
   for (int t = lane; t < kLd * kMaxM; t += kL) stc(H, t, C{0, 0});
@@ -293,7 +311,10 @@ struct DeflSmem {
 };
 
 __global__ void __launch_bounds__(kL)
-    k_deflate(double* H, int mm, int k, const double* c, const double* etag, double* Qg, double* ritz, double* scal) {
+    k_deflate(double* H, int mm, int k, const double* c, const double* etag, double* Qg, double* ritz, double* scal,
+              const int* gate, const int* dn) {
+  if (gate && *gate == 0) return;
+  if (dn) mm = *dn < mm ? *dn : mm;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   DeflSmem& S = *reinterpret_cast<DeflSmem*>(smem_raw);
   const int lane = threadIdx.x;
@@ -643,77 +664,79 @@ dw_status dense_step(double* H, int j, const double* h1, const double* h2, const
   return DW_OK;
 }
 
-dw_status dense_lsq(const double* H, int cols, const double* c, double* eta, double* scal, hipStream_t s) {
+dw_status dense_lsq(const double* H, int cols, const double* c, double* eta, double* scal, hipStream_t s,
+                    const int* gate, const int* dn) {
   if (cols < 1 || cols > kMaxM) {
     set_error("dense_lsq: %d columns out of range", cols);
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_lsq, sizeof(StepSmem)));
   KTimer kt(DW_K_DENSE, s);
-  hipLaunchKernelGGL(k_lsq, 1, kL, sizeof(StepSmem), s, H, cols, c, eta, scal);
+  hipLaunchKernelGGL(k_lsq, 1, kL, sizeof(StepSmem), s, H, cols, c, eta, scal, gate, dn);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;
 }
 
-dw_status dense_project(const double* H, int k, const double* t, double* y, double* sv, hipStream_t s) {
+dw_status dense_project(const double* H, int k, const double* t, double* y, double* sv, hipStream_t s,
+                        const int* gate) {
   if (k < 1 || k >= kMaxM) {
     set_error("dense_project: k = %d out of range", k);
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_project, sizeof(StepSmem)));
   KTimer kt(DW_K_DENSE, s);
-  hipLaunchKernelGGL(k_project, 1, kL, sizeof(StepSmem), s, H, k, t, y, sv);
+  hipLaunchKernelGGL(k_project, 1, kL, sizeof(StepSmem), s, H, k, t, y, sv, gate);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;
 }
 
 dw_status dense_deflate(double* H, int mm, int k, const double* c, const double* eta, double* Q, double* ritz,
-                        double* scal, hipStream_t s) {
+                        double* scal, hipStream_t s, const int* gate, const int* dn) {
   if (mm < 1 || mm > kMaxM || k < 1 || k >= mm || k + 1 > kQCols) {
     set_error("dense_deflate: unsupported sizes mm %d, k %d", mm, k);
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_deflate, sizeof(DeflSmem)));
   KTimer kt(DW_K_DENSE, s);
-  hipLaunchKernelGGL(k_deflate, 1, kL, sizeof(DeflSmem), s, H, mm, k, c, eta, Q, ritz, scal);
+  hipLaunchKernelGGL(k_deflate, 1, kL, sizeof(DeflSmem), s, H, mm, k, c, eta, Q, ritz, scal, gate, dn);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;
 }
 
 dw_status dense_gs_coef(double* H, int nv, int jcol, int jw, int hu, int hw, const double* red, double* coef,
-                        double* scal, double bd_tol, hipStream_t s) {
+                        double* scal, double bd_tol, hipStream_t s, const int* gate, const int* dcol) {
   (void)bd_tol;
   if (nv < 0 || nv > kLd || jcol > kMaxM || jw >= kMaxM || (hw && jw < 0) || (hu && jcol < 0)) {
     set_error("dense_gs_coef: bad sizes (nv %d, jcol %d, jw %d)", nv, jcol, jw);
     return DW_EINVAL;
   }
   KTimer kt(DW_K_DENSE, s);
-  hipLaunchKernelGGL(k_gs_coef, 1, kL, 0, s, H, nv, jcol, jw, hu, hw, red, coef, scal);
+  hipLaunchKernelGGL(k_gs_coef, 1, kL, 0, s, H, nv, jcol, jw, hu, hw, red, coef, scal, gate, dcol);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;
 }
 
 dw_status dense_step2(double* H, int j, const double* nrm2, const double* c, double* scal, double bd_tol,
-                      hipStream_t s) {
+                      hipStream_t s, int* ctl, const double* ctld) {
   if (j < 0 || j >= kMaxM) {
     set_error("dense_step2: column %d out of range", j);
     return DW_EINVAL;
   }
   DW_TRY(set_lds(k_step2, sizeof(StepSmem)));
   KTimer kt(DW_K_DENSE, s);
-  hipLaunchKernelGGL(k_step2, 1, kL, sizeof(StepSmem), s, H, j, nrm2, c, scal, bd_tol);
+  hipLaunchKernelGGL(k_step2, 1, kL, sizeof(StepSmem), s, H, j, nrm2, c, scal, bd_tol, ctl, ctld);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;
 }
 
-dw_status dense_fresh(double* H, double* c, const double* nrm2, double* scal, hipStream_t s) {
+dw_status dense_fresh(double* H, double* c, const double* nrm2, double* scal, hipStream_t s, const int* gate) {
   KTimer kt(DW_K_DENSE, s);
-  hipLaunchKernelGGL(k_fresh, 1, kL, 0, s, H, c, nrm2, scal);
+  hipLaunchKernelGGL(k_fresh, 1, kL, 0, s, H, c, nrm2, scal, gate);
   DW_CHECK_LAUNCH();
   kt.done(0, 0);
   return DW_OK;

@@ -95,12 +95,19 @@ __device__ __forceinline__ void blk_dir(const BlkCtx<T, SX, SG>& c, cplx<T> acc[
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
+// per-right-hand-side gate and device-side mass (both optional)
+struct DCtl {
+  const int* gate = nullptr;
+  int gstride = 0;
+  const double* dmass = nullptr;
+};
+
 // CLOV: add the clover term (site-local, dw_clover.hpp) from Cl.
 template <typename T, typename SX, typename SG, typename SY, int MODE, int MAXT, bool CLOV>
 __global__ void __launch_bounds__(MAXT)
     k_dslash_blk(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
                  const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist,
-                 const SG* __restrict__ Cl) {
+                 const SG* __restrict__ Cl, DCtl dc) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   SX* xsh = reinterpret_cast<SX*>(smem);
   cplx<T>* pb = reinterpret_cast<cplx<T>*>(smem + align16((size_t)12 * g.bvol * sizeof(SX)));
@@ -110,6 +117,8 @@ __global__ void __launch_bounds__(MAXT)
   if (wi < 0) return;  // uniform for the workgroup
   const int b = wi / nr;
   const int rhs = rlist ? rlist[wi - b * nr] : wi - b * nr;
+  if (dc.gate && dc.gate[(long long)rhs * dc.gstride] == 0) return;  // uniform for the workgroup
+  if (dc.dmass) diag = (T)(4.0 + *dc.dmass);
   const int l = threadIdx.x;
   const bool active = l < g.bvol;
   const SX* xr = x + (long long)rhs * xs;
@@ -169,12 +178,14 @@ template <typename T, typename SX, typename SG, typename SY, int MODE, bool CLOV
 __global__ void __launch_bounds__(kThreads)
     k_dslash(Geom g, T diag, const SX* __restrict__ x, T scale, const SG* __restrict__ U, SY* __restrict__ y,
              const SY* __restrict__ bsrc, long long xs, long long ys, int nr, const int* __restrict__ rlist,
-             const SG* __restrict__ Cl) {
+             const SG* __restrict__ Cl, DCtl dc) {
   const int chunk = xcd_remap(blockIdx.x, (int)((g.V + kThreads - 1) / kThreads));
   if (chunk < 0) return;
   const long long s = (long long)chunk * kThreads + threadIdx.x;
   if (s >= g.V) return;
   const int rhs = rlist ? rlist[blockIdx.y] : blockIdx.y;
+  if (dc.gate && dc.gate[(long long)rhs * dc.gstride] == 0) return;
+  if (dc.dmass) diag = (T)(4.0 + *dc.dmass);
   const SX* xr = x + (long long)rhs * xs;
   SY* yr = y + (long long)rhs * ys;
   const int b = (int)(s / g.bvol);
@@ -212,7 +223,7 @@ __global__ void __launch_bounds__(kThreads)
 
 template <typename T, typename SX, typename SG, typename SY, int MODE, bool CLOV>
 dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                     long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl);
+                     long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl, DCtl dc);
 
 dim3 grid_for(const Geom& g, int nrhs) {
   return dim3((unsigned)xcd_grid((int)((g.V + kThreads - 1) / kThreads)), (unsigned)nrhs);
@@ -220,7 +231,7 @@ dim3 grid_for(const Geom& g, int nrhs) {
 
 template <typename T, typename SX, typename SG, typename SY, int MODE, bool CLOV>
 dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                     long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl) {
+                     long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl, DCtl dc) {
   const size_t lds = blk_lds<T, SX>(g);
   const int threads = ((g.bvol + 63) / 64) * 64;
   if (lds <= 160 * 1024) {
@@ -233,7 +244,7 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
         }
       }
       dim3 grid((unsigned)xcd_grid(g.nblk * nrhs), 1);
-      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, Cl);
+      hipLaunchKernelGGL(kernel, grid, threads, lds, s, g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, Cl, dc);
       DW_CHECK_LAUNCH();
       return DW_OK;
     };
@@ -242,7 +253,7 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
     return launch_t(k_dslash_blk<T, SX, SG, SY, MODE, 1024, CLOV>);
   }
   hipLaunchKernelGGL((k_dslash<T, SX, SG, SY, MODE, CLOV>), grid_for(g, nrhs), kThreads, 0, s, g, diag, x, scale, U,
-                     y, b, xs, ys, nrhs, rlist, Cl);
+                     y, b, xs, ys, nrhs, rlist, Cl, dc);
   DW_CHECK_LAUNCH();
   return DW_OK;
 }
@@ -250,18 +261,23 @@ dw_status launch_any(const Geom& g, T diag, const SX* x, T scale, const SG* U, S
 // dispatch on the presence of a clover term
 template <typename T, typename SX, typename SG, typename SY, int MODE>
 dw_status launch_c(const Geom& g, T diag, const SX* x, T scale, const SG* U, SY* y, const SY* b, long long xs,
-                   long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl) {
-  if (Cl) return launch_any<T, SX, SG, SY, MODE, true>(g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, s, Cl);
-  return launch_any<T, SX, SG, SY, MODE, false>(g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, s, Cl);
+                   long long ys, int nrhs, const int* rlist, hipStream_t s, const SG* Cl, DCtl dc = DCtl{}) {
+  if (Cl) return launch_any<T, SX, SG, SY, MODE, true>(g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, s, Cl, dc);
+  return launch_any<T, SX, SG, SY, MODE, false>(g, diag, x, scale, U, y, b, xs, ys, nrhs, rlist, s, Cl, dc);
 }
 
 }  // namespace
 
 dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* x, double scale, const void* U64,
                               double* y, const double* b, int mode, int nrhs, long long xs, long long ys,
-                              hipStream_t s, const int* rlist, const void* C64) {
+                              hipStream_t s, const int* rlist, const void* C64, const int* gate, int gstride,
+                              const double* dmass) {
   if (nrhs < 1) return DW_OK;
   const double diag = 4.0 + m0;
+  DCtl dc;
+  dc.gate = gate;
+  dc.gstride = gstride;
+  dc.dmass = dmass;
   const s64* Ug = (const s64*)U64;
   const s64* Cg = (const s64*)C64;
   s64* yo = (s64*)y;
@@ -270,12 +286,12 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
   dw_status st;
   if (prec_x == DW_PREC_F64) {
     const s64* xi = (const s64*)x;
-    st = mode == 0 ? launch_c<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg)
-                   : launch_c<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg);
+    st = mode == 0 ? launch_c<double, s64, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg, dc)
+                   : launch_c<double, s64, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg, dc);
   } else if (prec_x == DW_PREC_F32) {
     const s32* xi = (const s32*)x;
-    st = mode == 0 ? launch_c<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg)
-                   : launch_c<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg);
+    st = mode == 0 ? launch_c<double, s32, s64, s64, 0>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg, dc)
+                   : launch_c<double, s32, s64, s64, 1>(g, diag, xi, scale, Ug, yo, bo, xs, ys, nrhs, rlist, s, Cg, dc);
   } else {
     set_error("outer dslash input precision must be F64 or F32");
     return DW_EINVAL;

@@ -13,9 +13,11 @@ constexpr int kThreads = 256;
 // complex numbers, writes 12 coalesced internal entries
 template <typename S>
 __global__ void __launch_bounds__(kThreads) k_pack_spinor(Geom g, const s64* __restrict__ in, S* __restrict__ out,
-                                                          double scale) {
+                                                          double scale, const double* __restrict__ dscale,
+                                                          int dstride) {
   long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (s >= g.V) return;
+  if (dscale) scale *= dscale[(long long)blockIdx.y * dstride];
   const long long rhs_off = (long long)blockIdx.y * g.V * 12;
   const int b = (int)(s / g.bvol);
   const int l = (int)(s - (long long)b * g.bvol);
@@ -30,9 +32,11 @@ __global__ void __launch_bounds__(kThreads) k_pack_spinor(Geom g, const s64* __r
 
 template <typename S>
 __global__ void __launch_bounds__(kThreads) k_unpack_spinor(Geom g, const S* __restrict__ in, s64* __restrict__ out,
-                                                            double scale) {
+                                                            double scale, const double* __restrict__ dscale,
+                                                            int dstride) {
   long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (s >= g.V) return;
+  if (dscale) scale *= dscale[(long long)blockIdx.y * dstride];
   const long long rhs_off = (long long)blockIdx.y * g.V * 12;
   const int b = (int)(s / g.bvol);
   const int l = (int)(s - (long long)b * g.bvol);
@@ -61,7 +65,9 @@ __global__ void __launch_bounds__(kThreads) k_pack_gauge(Geom g, const s64* __re
 
 template <typename SI, typename SO>
 __global__ void __launch_bounds__(kThreads) k_convert(const SI* __restrict__ in, SO* __restrict__ out, double scale,
-                                                      const double* __restrict__ dscale, long long n) {
+                                                      const double* __restrict__ dscale, long long n,
+                                                      const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   if (dscale) scale *= dscale[0];
   long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
   const long long stride = (long long)gridDim.x * kThreads;
@@ -73,15 +79,15 @@ dim3 site_grid(const Geom& g, int nrhs) { return dim3((unsigned)((g.V + kThreads
 }  // namespace
 
 dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* out, double scale, int nrhs,
-                             hipStream_t s) {
+                             hipStream_t s, const double* dscale, int dstride) {
   const s64* src = reinterpret_cast<const s64*>(in);
   dim3 grid = site_grid(g, nrhs);
   KTimer kt(DW_K_CONVERT, s);
   switch (prec) {
-    case DW_PREC_F64: hipLaunchKernelGGL(k_pack_spinor<s64>, grid, kThreads, 0, s, g, src, (s64*)out, scale); break;
-    case DW_PREC_F32: hipLaunchKernelGGL(k_pack_spinor<s32>, grid, kThreads, 0, s, g, src, (s32*)out, scale); break;
-    case DW_PREC_F16: hipLaunchKernelGGL(k_pack_spinor<s16>, grid, kThreads, 0, s, g, src, (s16*)out, scale); break;
-    case DW_PREC_BF16: hipLaunchKernelGGL(k_pack_spinor<sbf>, grid, kThreads, 0, s, g, src, (sbf*)out, scale); break;
+    case DW_PREC_F64: hipLaunchKernelGGL(k_pack_spinor<s64>, grid, kThreads, 0, s, g, src, (s64*)out, scale, dscale, dstride); break;
+    case DW_PREC_F32: hipLaunchKernelGGL(k_pack_spinor<s32>, grid, kThreads, 0, s, g, src, (s32*)out, scale, dscale, dstride); break;
+    case DW_PREC_F16: hipLaunchKernelGGL(k_pack_spinor<s16>, grid, kThreads, 0, s, g, src, (s16*)out, scale, dscale, dstride); break;
+    case DW_PREC_BF16: hipLaunchKernelGGL(k_pack_spinor<sbf>, grid, kThreads, 0, s, g, src, (sbf*)out, scale, dscale, dstride); break;
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
@@ -90,15 +96,15 @@ dw_status launch_pack_spinor(const Geom& g, int prec, const double* in, void* ou
 }
 
 dw_status launch_unpack_spinor(const Geom& g, int prec, const void* in, double* out, double scale, int nrhs,
-                               hipStream_t s) {
+                               hipStream_t s, const double* dscale, int dstride) {
   s64* dst = reinterpret_cast<s64*>(out);
   dim3 grid = site_grid(g, nrhs);
   KTimer kt(DW_K_CONVERT, s);
   switch (prec) {
-    case DW_PREC_F64: hipLaunchKernelGGL(k_unpack_spinor<s64>, grid, kThreads, 0, s, g, (const s64*)in, dst, scale); break;
-    case DW_PREC_F32: hipLaunchKernelGGL(k_unpack_spinor<s32>, grid, kThreads, 0, s, g, (const s32*)in, dst, scale); break;
-    case DW_PREC_F16: hipLaunchKernelGGL(k_unpack_spinor<s16>, grid, kThreads, 0, s, g, (const s16*)in, dst, scale); break;
-    case DW_PREC_BF16: hipLaunchKernelGGL(k_unpack_spinor<sbf>, grid, kThreads, 0, s, g, (const sbf*)in, dst, scale); break;
+    case DW_PREC_F64: hipLaunchKernelGGL(k_unpack_spinor<s64>, grid, kThreads, 0, s, g, (const s64*)in, dst, scale, dscale, dstride); break;
+    case DW_PREC_F32: hipLaunchKernelGGL(k_unpack_spinor<s32>, grid, kThreads, 0, s, g, (const s32*)in, dst, scale, dscale, dstride); break;
+    case DW_PREC_F16: hipLaunchKernelGGL(k_unpack_spinor<s16>, grid, kThreads, 0, s, g, (const s16*)in, dst, scale, dscale, dstride); break;
+    case DW_PREC_BF16: hipLaunchKernelGGL(k_unpack_spinor<sbf>, grid, kThreads, 0, s, g, (const sbf*)in, dst, scale, dscale, dstride); break;
     default: set_error("unknown precision %d", prec); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
@@ -125,15 +131,15 @@ dw_status launch_pack_gauge(const Geom& g, int prec, const double* in, void* out
 namespace {
 template <typename SI>
 dw_status convert_from(const SI* in, int pout, void* out, double scale, const double* ds, long long n,
-                       hipStream_t s) {
+                       hipStream_t s, const int* gate) {
   long long nb = (n + kThreads - 1) / kThreads;
   unsigned grid = (unsigned)(nb < 8192 ? (nb > 0 ? nb : 1) : 8192);
   KTimer kt(DW_K_CONVERT, s);
   switch (pout) {
-    case DW_PREC_F64: hipLaunchKernelGGL((k_convert<SI, s64>), grid, kThreads, 0, s, in, (s64*)out, scale, ds, n); break;
-    case DW_PREC_F32: hipLaunchKernelGGL((k_convert<SI, s32>), grid, kThreads, 0, s, in, (s32*)out, scale, ds, n); break;
-    case DW_PREC_F16: hipLaunchKernelGGL((k_convert<SI, s16>), grid, kThreads, 0, s, in, (s16*)out, scale, ds, n); break;
-    case DW_PREC_BF16: hipLaunchKernelGGL((k_convert<SI, sbf>), grid, kThreads, 0, s, in, (sbf*)out, scale, ds, n); break;
+    case DW_PREC_F64: hipLaunchKernelGGL((k_convert<SI, s64>), grid, kThreads, 0, s, in, (s64*)out, scale, ds, n, gate); break;
+    case DW_PREC_F32: hipLaunchKernelGGL((k_convert<SI, s32>), grid, kThreads, 0, s, in, (s32*)out, scale, ds, n, gate); break;
+    case DW_PREC_F16: hipLaunchKernelGGL((k_convert<SI, s16>), grid, kThreads, 0, s, in, (s16*)out, scale, ds, n, gate); break;
+    case DW_PREC_BF16: hipLaunchKernelGGL((k_convert<SI, sbf>), grid, kThreads, 0, s, in, (sbf*)out, scale, ds, n, gate); break;
     default: set_error("unknown precision %d", pout); return DW_EINVAL;
   }
   DW_CHECK_LAUNCH();
@@ -143,12 +149,12 @@ dw_status convert_from(const SI* in, int pout, void* out, double scale, const do
 }  // namespace
 
 dw_status launch_convert(int pin, const void* in, int pout, void* out, double scale, long long n, hipStream_t s,
-                         const double* dscale) {
+                         const double* dscale, const int* gate) {
   switch (pin) {
-    case DW_PREC_F64: return convert_from((const s64*)in, pout, out, scale, dscale, n, s);
-    case DW_PREC_F32: return convert_from((const s32*)in, pout, out, scale, dscale, n, s);
-    case DW_PREC_F16: return convert_from((const s16*)in, pout, out, scale, dscale, n, s);
-    case DW_PREC_BF16: return convert_from((const sbf*)in, pout, out, scale, dscale, n, s);
+    case DW_PREC_F64: return convert_from((const s64*)in, pout, out, scale, dscale, n, s, gate);
+    case DW_PREC_F32: return convert_from((const s32*)in, pout, out, scale, dscale, n, s, gate);
+    case DW_PREC_F16: return convert_from((const s16*)in, pout, out, scale, dscale, n, s, gate);
+    case DW_PREC_BF16: return convert_from((const sbf*)in, pout, out, scale, dscale, n, s, gate);
     default: set_error("unknown precision %d", pin); return DW_EINVAL;
   }
 }

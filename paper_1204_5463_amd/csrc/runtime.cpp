@@ -10,6 +10,7 @@
 #include <string>
 
 #include "dw_clover.hpp"
+#include "dw_control.hpp"
 #include "dw_internal.hpp"
 #include "dw_kernels.hpp"
 #include <math.h>
@@ -29,10 +30,13 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_last_error.clear(); }
 
+// Without a caller allocator, memory is stream-ordered (hipMallocAsync /
+// hipFreeAsync on the call's stream), so that freeing a temporary at the end
+// of an asynchronous call does not synchronise the device.
 void* dev_alloc(dw_ctx ctx, size_t bytes, hipStream_t stream) {
   if (ctx->user_alloc) return ctx->alloc.alloc(bytes, stream, ctx->alloc.user);
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  if (hipMallocAsync(&p, bytes, stream) != hipSuccess) return nullptr;
   return p;
 }
 
@@ -42,8 +46,7 @@ void dev_free(dw_ctx ctx, void* p, hipStream_t stream) {
     ctx->alloc.release(p, stream, ctx->alloc.user);
     return;
   }
-  // hipFree synchronises the device; callers free only at the end of a call
-  (void)hipFree(p);
+  (void)hipFreeAsync(p, stream);
 }
 
 }  // namespace dw
@@ -190,6 +193,7 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
 dw_status dw_field_destroy(dw_field f) {
   clear_error();
   if (!f) return DW_OK;
+  if (f->solver_cache) f->solver_cache_free(f->solver_cache);
   for (int p = 0; p < 4; ++p) {
     dev_free(f->ctx, f->U[p], f->stream);
     dev_free(f->ctx, f->C[p], f->stream);
@@ -206,6 +210,13 @@ dw_status dw_field_set_clover(dw_field f, double csw, hipStream_t stream) {
   }
   DW_TRY(check_device(f->ctx));
   ProfScope ps(f->ctx);
+  if (f->solver_cache) {
+    // captured solver cycles read the old term
+    DW_CHECK_HIP(hipStreamSynchronize(stream));
+    f->solver_cache_free(f->solver_cache);
+    f->solver_cache = nullptr;
+    f->solver_cache_free = nullptr;
+  }
   for (int p = 0; p < 4; ++p) {
     dev_free(f->ctx, f->C[p], stream);
     f->C[p] = nullptr;
@@ -233,6 +244,33 @@ dw_status dw_field_set_clover(dw_field f, double csw, hipStream_t stream) {
 
 int64_t dw_field_volume(dw_field f) { return f ? (int64_t)f->g.V : 0; }
 
+}  // extern "C"
+
+namespace dw {
+
+// Loads new links into an existing field in place (same lattice, block and
+// presence of the clover term), keeping its buffers, so that captured solver
+// cycles that read them stay valid. Asynchronous on `stream`.
+dw_status field_reload(dw_field f, const double* U_dev, double csw, hipStream_t stream) {
+  if (!f || !U_dev || (csw != 0.0) != (f->C[DW_PREC_F64] != nullptr) || !std::isfinite(csw)) {
+    set_error("field_reload: invalid argument");
+    return DW_EINVAL;
+  }
+  DW_TRY(check_device(f->ctx));
+  for (int p = 0; p < 4; ++p) DW_TRY(launch_pack_gauge(f->g, p, U_dev, f->U[p], stream));
+  f->csw = csw;
+  if (csw != 0.0) {
+    const long long n = f->g.V * kCloverPairs;
+    DW_TRY(launch_clover_build(f->g, f->U[DW_PREC_F64], csw, (double*)f->C[DW_PREC_F64], stream));
+    for (int p = 1; p < 4; ++p) DW_TRY(launch_convert(DW_PREC_F64, f->C[DW_PREC_F64], p, f->C[p], 1.0, n, stream));
+  }
+  return DW_OK;
+}
+
+}  // namespace dw
+
+extern "C" {
+
 size_t dw_internal_bytes(dw_field f, int32_t prec, int32_t nrhs) {
   if (!f || prec < 0 || prec > 3 || nrhs < 0) return 0;
   return (size_t)f->g.V * 12 * pair_bytes(prec) * (size_t)nrhs;
@@ -259,9 +297,7 @@ dw_status dw_apply(dw_field f, double m0, const double* x, double* y, int32_t nr
   DW_TRY(launch_pack_spinor(g, DW_PREC_F64, x, xi.p, 1.0, nrhs, stream));
   DW_TRY(launch_dslash_outer(g, m0, DW_PREC_F64, xi.p, 1.0, f->U[DW_PREC_F64], yi.as<double>(), nullptr, 0, nrhs,
                              (long long)n, (long long)n, stream, nullptr, f->C[DW_PREC_F64]));
-  DW_TRY(launch_unpack_spinor(g, DW_PREC_F64, yi.p, y, 1.0, nrhs, stream));
-  DW_CHECK_HIP(hipStreamSynchronize(stream));
-  return DW_OK;
+  return launch_unpack_spinor(g, DW_PREC_F64, yi.p, y, 1.0, nrhs, stream);
 }
 
 size_t dw_apply_noalloc_max_bytes(void) { return kScratchBytes; }
@@ -394,33 +430,29 @@ extern "C" dw_status sap_precondition(dw_field f, double m0, const sap_params* s
   const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
   if (sp->ncycles == 0) {
     DW_CHECK_HIP(hipMemsetAsync(z, 0, (size_t)n * 16 * nrhs, stream));
-    DW_CHECK_HIP(hipStreamSynchronize(stream));
     return DW_OK;
   }
-  DevBuf vi, zi, part, nrm;
-  DW_TRY(vi.alloc(f->ctx, (size_t)n * pair_bytes(prec), stream));
-  DW_TRY(zi.alloc(f->ctx, (size_t)n * pair_bytes(zprec), stream));
-  DW_TRY(part.alloc(f->ctx, (size_t)kBlasGrid * 16, stream));
-  DW_TRY(nrm.alloc(f->ctx, 16, stream));
-  for (int r = 0; r < nrhs; ++r) {
-    const double* vr = v + 2 * (long long)r * n;
-    double* zr = z + 2 * (long long)r * n;
+  DevBuf vi, zi, part, nrm, sc;
+  DW_TRY(vi.alloc(f->ctx, (size_t)n * pair_bytes(prec) * nrhs, stream));
+  DW_TRY(zi.alloc(f->ctx, (size_t)n * pair_bytes(zprec) * nrhs, stream));
+  if (prec != DW_PREC_F64) {
     // M is scale-equivariant (M(a v) = a M(v)); low-precision storage gets
-    // v scaled to unit RMS per entry so that FP16 keeps its range.
-    double sigma = 1.0;
-    if (prec != DW_PREC_F64) {
-      DW_TRY(blas_dots(DW_PREC_F64, vr, n, 1, vr, n, part.as<double>(), nrm.as<double>(), 1, 0, stream));
-      double h[2];
-      DW_CHECK_HIP(hipMemcpyAsync(h, nrm.p, sizeof h, hipMemcpyDeviceToHost, stream));
-      DW_CHECK_HIP(hipStreamSynchronize(stream));
-      if (h[0] > 0) sigma = sqrt((double)n / h[0]);
+    // each v scaled to unit RMS per entry so that FP16 keeps its range (the
+    // factor is formed on the device, so the call does not synchronise)
+    DW_TRY(part.alloc(f->ctx, (size_t)kBlasGrid * 16, stream));
+    DW_TRY(nrm.alloc(f->ctx, (size_t)nrhs * 16, stream));
+    DW_TRY(sc.alloc(f->ctx, (size_t)nrhs * 16, stream));
+    for (int r = 0; r < nrhs; ++r) {
+      const double* vr = v + 2 * (long long)r * n;
+      DW_TRY(blas_dots(DW_PREC_F64, vr, n, 1, vr, n, part.as<double>(), nrm.as<double>() + 2 * r, 1, 0, stream));
     }
-    DW_TRY(launch_pack_spinor(g, prec, vr, vi.p, sigma, 1, stream));
-    DW_TRY(sap_apply_internal(f, m0, sp, vi.p, zi.p, 1, stream));
-    DW_TRY(launch_unpack_spinor(g, zprec, zi.p, zr, 1.0 / sigma, 1, stream));
+    DW_TRY(rms_scales(nrm.as<double>(), n, sc.as<double>(), nrhs, stream));
   }
-  DW_CHECK_HIP(hipStreamSynchronize(stream));
-  return DW_OK;
+  const double* sig = prec != DW_PREC_F64 ? sc.as<double>() : nullptr;
+  const double* isig = prec != DW_PREC_F64 ? sc.as<double>() + 1 : nullptr;
+  DW_TRY(launch_pack_spinor(g, prec, v, vi.p, 1.0, nrhs, stream, sig, 2));
+  DW_TRY(sap_apply_internal(f, m0, sp, vi.p, zi.p, nrhs, stream));
+  return launch_unpack_spinor(g, zprec, zi.p, z, 1.0, nrhs, stream, isig, 2);
 }
 
 extern "C" dw_status sap_solve(dw_field f, double m0, const sap_params* sp, const double* b, double* x, int32_t niter,

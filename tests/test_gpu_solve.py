@@ -174,10 +174,10 @@ def test_shared_deflation_space():
 
 
 def test_graph_captured_steps_equal_eager(c1):
-    """Arnoldi steps captured as HIP graphs and replayed in later cycles give
-    bit for bit the eager solve (many short cycles, so every graph is
-    replayed many times with the host's own synchronisation in between);
-    on the default stream the flag is ignored."""
+    """Restart cycles captured as HIP graphs and replayed give bit for bit the
+    eager solve (many short cycles, so every graph is replayed many times
+    with the host's own synchronisation in between, and again by the next
+    solve on the field); on the default stream the flag is ignored."""
     import torch
     U, b, f, xo, info = c1
     st = torch.cuda.Stream()
