@@ -26,6 +26,7 @@
 
 namespace dw {
 size_t solver_bytes(long long sites, int m, int prec, int flags, int nrhs);
+dw_status field_reload(dw_field f, const double* U_dev, double csw, hipStream_t stream);
 }
 
 using namespace dw;
@@ -72,10 +73,36 @@ struct dw_server_s {
 
 namespace {
 
+// A slot keeps the field of its last request (its link copies, and with
+// them the solver's workspace and captured restart cycles) while the next
+// request it takes has the same lattice, block and clover presence: the new
+// links are loaded into the same buffers and the captured cycles are
+// replayed (the solver keeps them for equal parameters and RHS count).
+// Otherwise, and whenever the slot goes idle, the field is freed, so the
+// memory the slot holds is always that of the request it is charged for.
+struct SlotField {
+  dw_field f = nullptr;
+  int L[4] = {}, block[4] = {};
+  bool clover = false;
+  bool matches(const dw_request& r) const {
+    if (!f || (r.csw != 0.0) != clover) return false;
+    for (int i = 0; i < 4; ++i)
+      if (L[i] != r.L[i] || block[i] != r.block[i]) return false;
+    return true;
+  }
+  void drop(hipStream_t st) {
+    if (!f) return;
+    (void)hipStreamSynchronize(st);
+    dw_field_destroy(f);
+    f = nullptr;
+  }
+};
+
 void worker(dw_server s) {
   (void)hipSetDevice(s->ictx->device);
   hipStream_t st = nullptr;
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  SlotField held;
   while (true) {
     std::shared_ptr<Req> rq;
     {
@@ -101,6 +128,12 @@ void worker(dw_server s) {
           }
         return false;
       };
+      if (!admissible() && held.f) {
+        // going idle: give the held field back before waiting
+        lk.unlock();
+        held.drop(st);
+        lk.lock();
+      }
       s->cv.wait(lk, [&] { return admissible() || (s->stop && s->queue.empty()); });
       if (s->queue.empty()) break;
       rq = s->queue[pick];
@@ -112,23 +145,44 @@ void worker(dw_server s) {
     dw_status status = have_stream ? DW_OK : DW_EHIP;
     std::string err = have_stream ? "" : "could not create a stream for the server slot";
     if (status == DW_OK) {
-      dw_field f = nullptr;
-      status = dw_field_create(s->ictx, rq->r.L, rq->r.block, rq->r.U, st, &f);
-      if (status == DW_OK && rq->r.csw != 0.0) {
-        status = dw_field_set_clover(f, rq->r.csw, st);
+      if (held.matches(rq->r)) {
+        status = field_reload(held.f, rq->r.U, rq->r.csw, st);
         if (status != DW_OK) {
           err = dw_last_error();
-          dw_field_destroy(f);
-          f = nullptr;
+          held.drop(st);
+        }
+      } else {
+        held.drop(st);
+        dw_field f = nullptr;
+        status = dw_field_create(s->ictx, rq->r.L, rq->r.block, rq->r.U, st, &f);
+        if (status == DW_OK && rq->r.csw != 0.0) {
+          status = dw_field_set_clover(f, rq->r.csw, st);
+          if (status != DW_OK) {
+            err = dw_last_error();
+            dw_field_destroy(f);
+            f = nullptr;
+          }
+        } else if (status != DW_OK) {
+          err = dw_last_error();
+        }
+        if (status == DW_OK) {
+          held.f = f;
+          for (int i = 0; i < 4; ++i) {
+            held.L[i] = rq->r.L[i];
+            held.block[i] = rq->r.block[i];
+          }
+          held.clover = rq->r.csw != 0.0;
         }
       }
       if (status == DW_OK) {
-        status = fgmresdr_solve(f, rq->r.m0, &rq->r.params, rq->r.b, rq->r.x, rq->r.nrhs, rq->stats.data(), st);
-        if (status != DW_OK && status != DW_ENOTCONV) err = dw_last_error();
-        (void)hipStreamSynchronize(st);
-        dw_field_destroy(f);
-      } else {
-        err = dw_last_error();
+        // every request runs on captured restart cycles
+        fgmresdr_params prm = rq->r.params;
+        prm.flags |= DW_SOLVE_GRAPHS;
+        status = fgmresdr_solve(held.f, rq->r.m0, &prm, rq->r.b, rq->r.x, rq->r.nrhs, rq->stats.data(), st);
+        if (status != DW_OK && status != DW_ENOTCONV) {
+          err = dw_last_error();
+          held.drop(st);
+        }
       }
       (void)hipStreamSynchronize(st);
     }
@@ -141,6 +195,7 @@ void worker(dw_server s) {
     }
     s->cv.notify_all();
   }
+  held.drop(st);
   if (have_stream) (void)hipStreamDestroy(st);
 }
 

@@ -135,3 +135,44 @@ def test_destroy_drains_queue(dwctx, reqs):
     assert time.time() - t0 < 60
     xa, _ = _alone(dwctx, U, b, m0, prm)
     assert np.array_equal(x.cpu().numpy(), xa)
+
+
+def test_slot_reuses_field_and_captured_cycles(dwctx):
+    """One slot, back-to-back requests of one lattice and parameter set with
+    new links, masses and right-hand sides each time: the slot loads the
+    links into the field it holds and replays the restart cycles captured
+    for the first request. Every result equals the same solve made alone,
+    bit for bit, and a request of another lattice in between changes
+    nothing."""
+    prm = _params()
+    cases = [(0.3, -0.1, 11, 1), (0.35, -0.2, 12, 1), (0.3, -0.05, 13, 1)]
+    data = []
+    for eps, m0, seed, nrhs in cases:
+        U = synth.gauge_field(L, eps, seed)
+        b = synth.gaussian_spinors(L, nrhs, seed0=3000 + seed)
+        data.append((U, b, m0))
+    L2 = (8, 8, 8, 16)
+    U2 = synth.gauge_field(L2, 0.3, 5)
+    b2 = synth.gaussian_spinor(L2, 3100)[None]
+    alone = [_alone(dwctx, U, b, m0, prm) for U, b, m0 in data]
+    f2 = P.Field(dwctx, L2, B, P.to_device(U2))
+    x2a, _ = f2.solve(-0.1, prm, P.to_device(b2))
+    x2a = x2a.cpu().numpy()
+    f2.close()
+    srv = P.Server(dwctx, slots=1, queue_capacity=8)
+    try:
+        dev = [(P.to_device(U), P.to_device(b), m0) for U, b, m0 in data]
+        t = [srv.submit(L, B, m0, Ud, bd, prm) for Ud, bd, m0 in dev[:2]]
+        t.append(srv.submit(L2, B, -0.1, P.to_device(U2), P.to_device(b2), prm))
+        t.append(srv.submit(L, B, dev[2][2], dev[2][0], dev[2][1], prm))
+        res = [srv.wait(q) for q in t]
+    finally:
+        srv.close()
+    order = [0, 1, None, 2]
+    for i, (x, st, tm) in zip(order, res):
+        if i is None:
+            assert np.array_equal(x.cpu().numpy(), x2a)
+            continue
+        xa, sa = alone[i]
+        assert np.array_equal(x.cpu().numpy(), xa), i
+        assert [s.iterations for s in st] == [s.iterations for s in sa]
