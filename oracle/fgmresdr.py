@@ -20,7 +20,12 @@ Test infrastructure only. Follows the paper's Section 4:
   * optionally (``inject``) the explicit residual also enters G_{k+1} in
     place of the small residual c - H^ eta (as V_{m+1}^H r), and becomes the
     last vector v_{k+1} after orthonormalisation against the rotated V_k,
-    as Section 4.7 does for its low-precision Arnoldi.
+    as Section 4.7 does for its low-precision Arnoldi;
+  * optionally (``A_low``) the low-precision Arnoldi of Section 4.7: the
+    bases V and Z are stored in single precision, w = A z_j comes from the
+    low-precision operator A_low on the stored z_j and is orthogonalised in
+    single-precision arithmetic; the iterate, the explicit residual, its
+    injection and the small dense problems stay in double precision.
 
 Readings taken where the paper is silent:
   * m is the total basis size including the k deflation vectors; cycles
@@ -138,13 +143,15 @@ def flexible_arnoldi(A, M, b, m):
 
 
 def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
-             breakdown_tol=1e-14, keep_basis=False, inject=False):
+             breakdown_tol=1e-14, keep_basis=False, inject=False, A_low=None):
     """Solve A x = b by FGMRES-DR(m, k) (Alg. 4) from x0 = 0.
 
     A, M: callables on flat complex vectors. M may change from call to call
-    (flexible preconditioning). Returns (x, SolveInfo) and, with
-    ``keep_basis``, also (V, Z, H^) of the last cycle, cut to the steps
-    that cycle performed.
+    (flexible preconditioning). A_low (optional): the low-precision
+    operator, a callable on complex64 vectors returning complex64; given,
+    the Arnoldi process runs in single precision (Section 4.7). Returns
+    (x, SolveInfo) and, with ``keep_basis``, also (V, Z, H^) of the last
+    cycle, cut to the steps that cycle performed.
     """
     if not (0 <= k < m):
         raise ValueError("need 0 <= k < m")
@@ -153,8 +160,11 @@ def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
     bnorm = float(np.linalg.norm(b))
     x = np.zeros(n, dtype=np.complex128)
     r = b.copy()
-    V = np.zeros((n, m + 1), dtype=np.complex128)
-    Z = np.zeros((n, m), dtype=np.complex128)
+    # basis storage: assignments into single-precision arrays round to them
+    basis = np.complex64 if A_low is not None else np.complex128
+    A_arnoldi = A_low if A_low is not None else A
+    V = np.zeros((n, m + 1), dtype=basis)
+    Z = np.zeros((n, m), dtype=basis)
     H = np.zeros((m + 1, m), dtype=np.complex128)
     c = np.zeros(m + 1, dtype=np.complex128)
     iters = cycles = clean = 0
@@ -182,7 +192,7 @@ def fgmresdr(A, M, b, m, k, tol=1e-10, max_iter=10000, t_clean=5.0,
         broke = False
         # flexible Arnoldi steps j0 .. m-1 (0-based column index)
         for j in range(j0, m):
-            w = arnoldi_step(A, M, V, Z, H, j)
+            w = arnoldi_step(A_arnoldi, M, V, Z, H, j)
             iters += 1
             jend = j + 1
             hnorm = np.linalg.norm(H[:j + 2, :j + 1])

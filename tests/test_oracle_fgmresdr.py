@@ -270,3 +270,49 @@ def test_injection_follows_plain_solve_in_fp64():
     assert np.max(np.abs(h0[:nh] - h1[:nh]) / h0[:nh]) < 1e-6
     assert np.linalg.norm(x0 - x1) < 1e-9 * np.linalg.norm(x0)
 
+
+
+def _low_op(U, m0, shp):
+    """The operator on single-precision links and vectors, result rounded to single."""
+    U32 = U.astype(np.complex64)
+    return lambda v: W.apply_D(U32, m0, np.asarray(v, dtype=np.complex64).reshape(shp)).reshape(-1).astype(
+        np.complex64)
+
+
+def test_low_precision_arnoldi_is_single_precision():
+    """With A_low the Arnoldi basis is single precision: V is orthonormal and
+    A_low Z = V H^ holds only to single-precision rounding (not to double)."""
+    L = (4, 4, 4, 4)
+    U, A, M = _ops(L, 0.3, 0, -0.1)
+    shp = synth.lattice_shape(L) + (4, 3)
+    Al = _low_op(U, -0.1, shp)
+    b = synth.gaussian_spinor(L, 1000).reshape(-1)
+    _, info, (V, Z, H) = F.fgmresdr(A, M, b, 12, 0, tol=1e-30, max_iter=12, keep_basis=True, A_low=Al)
+    assert V.dtype == np.complex64 and Z.dtype == np.complex64
+    V64, Z64 = V.astype(np.complex128), Z.astype(np.complex128)
+    orth = np.linalg.norm(V64.conj().T @ V64 - np.eye(V.shape[1]))
+    assert 1e-9 < orth < 1e-5, orth
+    AZ = np.stack([A(Z64[:, j]) for j in range(Z.shape[1])], axis=1)
+    rel = np.linalg.norm(AZ - V64 @ H) / np.linalg.norm(H)
+    assert 1e-10 < rel < 1e-5, rel
+
+
+def test_low_precision_arnoldi_with_injection_reaches_fp64_residual():
+    """Section 4.7: a single-precision Arnoldi with the explicit FP64 residual
+    entering each restart (c, G_{k+1}, v_{k+1}) still reaches a 1e-10 true
+    residual in FP64, in about the iterations of the double-precision solve;
+    the solution agrees with dense LU within the conditioning bound."""
+    L = (4, 4, 4, 4)
+    m0 = -0.1
+    U, A, M = _ops(L, 0.3, 0, m0)
+    shp = synth.lattice_shape(L) + (4, 3)
+    Al = _low_op(U, m0, shp)
+    b = synth.gaussian_spinor(L, 1000).reshape(-1)
+    x64, i64 = F.fgmresdr(A, M, b, 8, 3, tol=1e-10, max_iter=400)
+    x32, i32 = F.fgmresdr(A, M, b, 8, 3, tol=1e-10, max_iter=400, inject=True, A_low=Al)
+    assert i64.converged and i32.converged
+    assert np.linalg.norm(b - A(x32)) <= 1e-10 * np.linalg.norm(b)
+    assert i32.iterations <= 1.5 * i64.iterations + 8, (i32.iterations, i64.iterations)
+    Dd = W.dense_D(U, m0)
+    xs = np.linalg.solve(Dd, b)
+    assert np.linalg.norm(x32 - xs) <= 1e-8 * np.linalg.norm(xs)
