@@ -28,8 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
-FP64_VALU_PEAK_TFLOPS = 78.6
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X published FP64 vector peak
 
 WORKLOADS = {
     # name: lattice, eps, gauge seed, mass spec, SAP, solver
@@ -40,7 +40,8 @@ WORKLOADS = {
     # s = 8, nMR = 9, the optimum of a search capped at s = 8, needs 37
     # iterations and 6% more time; the starting point s = 2, nMR = 5 needs
     # 152 iterations and 2.5x the time
-    "32^3x64": dict(L=(32, 32, 32, 64), eps=0.7, seed=0, mass=(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
+    "32^3x64": dict(L=(32, 32, 32, 64), eps=0.7, seed=0,
+                    mass=(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
                     block=(4, 4, 4, 4), ncycles=13, nmr=8, storage="f16", m=30, k=12),
     "16^3x32": dict(L=(16, 16, 16, 32), eps=0.6, seed=0, mass=(("16^3x32_eps0.6", "12^4_eps0.6"), 0.001),
                     block=(4, 4, 4, 4), ncycles=2, nmr=5, storage="f32", m=30, k=10),
@@ -51,7 +52,8 @@ WORKLOADS = {
     # bases fit in one GPU's memory; block shape, cycles and MR steps from the
     # tuning (the starting point 8x4x4x4, s = 2, nMR = 5 takes 168 iterations
     # and 2.6x the time)
-    "32^3x64x12": dict(L=(32, 32, 32, 64), eps=0.7, seed=0, mass=(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
+    "32^3x64x12": dict(L=(32, 32, 32, 64), eps=0.7, seed=0,
+                       mass=(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
                        block=(4, 4, 4, 4), ncycles=13, nmr=8, storage="f16", m=20, k=8, nrhs=12, rhs="point"),
     # the same lattice with the clover term (c_sw = 1.9, as in the paper's
     # experiments), near the critical mass of the clover operator; the SAP
@@ -68,7 +70,8 @@ WORKLOADS = {
 SERVE_LATTICES = {"8^4": (8, 8, 8, 8), "16^3x32": (16, 16, 16, 32), "24^3x48": (24, 24, 24, 48),
                   "32^3x64": (32, 32, 32, 64)}
 SERVE_MASS = {"8^4": ("8^4_eps0.6",), "16^3x32": ("16^3x32_eps0.6", "12^4_eps0.6"),
-              "24^3x48": ("16^3x32_eps0.6", "12^4_eps0.6"), "32^3x64": ("16^3x32_eps0.6", "12^4_eps0.6")}
+              "24^3x48": ("24^3x48_eps0.6", "16^3x32_eps0.6", "12^4_eps0.6"),
+              "32^3x64": ("32^3x64_eps0.6", "16^3x32_eps0.6", "12^4_eps0.6")}
 
 
 def log(*a):
@@ -77,8 +80,9 @@ def log(*a):
 
 def mass_for(spec):
     """m0 = m_c + delta with m_c = -Re(leftmost eigenvalue of D(0)), computed
-    by the oracle for the largest lattice of the same link distribution that
-    has been tuned (tests/golden/critical_mass.json). Returns (m0, source)."""
+    by the oracle's ARPACK run on the workload's own lattice where available,
+    else on the largest lattice of the same link distribution that has been
+    tuned (tests/golden/critical_mass.json). Returns (m0, source)."""
     names, delta = spec
     if names is None:
         return delta, "fixed"
@@ -117,26 +121,28 @@ def measured_traffic(key):
     return ent["bytes_per_launch"]
 
 
-def time_dslash(P, torch, f, m0, prec, reps=50, warm=10):
-    """Average kernel time of D at storage precision prec (events on the launch stream)."""
+def time_dslash(P, torch, f, m0, prec, reps=50, warm=10, nrhs=1):
+    """Average kernel time of D at storage precision prec (events on the launch
+    stream) for nrhs right-hand sides in one launch."""
     V = f.volume
-    x = torch.randn((V * 12, 2), dtype=torch.float64, device="cuda")
+    x = torch.randn((nrhs * V * 12, 2), dtype=torch.float64, device="cuda")
     xc = torch.view_as_complex(x)
     xi = f.pack(prec, xc)
     yi = torch.empty_like(xi)
     del x, xc
     for _ in range(warm):
-        f.apply_ex(m0, prec, xi, yi)
+        f.apply_ex(m0, prec, xi, yi, nrhs=nrhs)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        f.apply_ex(m0, prec, xi, yi)
+        f.apply_ex(m0, prec, xi, yi, nrhs=nrhs)
     e1.record(s)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    # x read, 4 links read, y written (+ the clover term's 36 pairs)
-    nbytes = V * (60 + (36 if getattr(f, "csw", 0.0) else 0)) * P.PAIR_BYTES[prec]
+    # links read once (36 pairs, + the clover term's 36), x read and y written
+    # once per right-hand side (24 pairs)
+    nbytes = V * ((36 + (36 if getattr(f, "csw", 0.0) else 0)) + 24 * nrhs) * P.PAIR_BYTES[prec]
     del xi, yi
     return ms, nbytes / ms / 1e6
 
@@ -200,6 +206,10 @@ def cpu_baseline(L, eps, seed, m0, wl, iterations, cycles):
                    f"NumPy single-threaded on {platform.processor() or platform.machine()}, os.cpu_count()="
                    f"{os.cpu_count()}"),
     }
+
+
+def csw_requested(args, wl):
+    return bool(args.csw or wl.get("csw", 0.0))
 
 
 def solver_params(P, wl, prec, tuned=None):
@@ -560,12 +570,36 @@ def main():
     unprofiled_ms = 1000 * (time.perf_counter() - ts)
     log(f"[bench] solve without event timing: {unprofiled_ms:.1f} ms")
 
-    # independent FP64 residual check of the last solutions (library FP64 operator)
-    relres_check = 0.0
-    for j in range(nrhs):
-        r = bt[j] - f.apply(m0, x[j].contiguous())
-        relres_check = max(relres_check, float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(bt[j])))
-    del r
+    # the same solve replayed from captured restart cycles (DW_SOLVE_GRAPHS;
+    # no per-launch event timing), wall clock over a few solves
+    graph_fig = None
+    if not (params.flags & P.SOLVE_GRAPHS):
+        pg = dataclasses.replace(params, flags=params.flags | P.SOLVE_GRAPHS)
+        f.solve(m0, pg, bt)  # captures
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        ts = time.perf_counter()
+        for _ in range(reps):
+            _, sg = f.solve(m0, pg, bt)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - ts) / reps
+        graph_fig = {"solves_per_s": round(nrhs / tg, 4), "ms_per_solve": round(1000 * tg, 2),
+                     "iterations": max(s.iterations for s in sg)}
+        log(f"[bench] solve replayed from captured cycles: {1000 * tg:.1f} ms")
+
+    # FP64 residual check of the last solutions by the oracle's operator (eq. 1)
+    # on the host, outside the timed region
+    relres_oracle = None
+    if not csw_requested(args, wl):
+        from oracle import wilson as W
+        log("[bench] oracle residual of the final solution")
+        xh = x.cpu().numpy()
+        Uh = synth.gauge_field(L, wl["eps"], wl["seed"])
+        relres_oracle = 0.0
+        for j in range(nrhs):
+            r = b[j] - W.apply_D(Uh, m0, xh[j])
+            relres_oracle = max(relres_oracle, float(np.linalg.norm(r) / np.linalg.norm(b[j])))
+        del Uh, xh, r
 
     # dominant kernel class in the timed region
     dom = max(kern, key=lambda k: kern[k]["ms"])
@@ -581,9 +615,12 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     roofline["traffic"] = measured_traffic(f"{dom}/{args.workload}/{wl['storage']}")
+    alg_bytes = kd["bytes"] / max(1, kd["launches"])
     roofline.update({"kernel_class": dom, "avg_launch_ms": round(avg_ms, 4), "launches": kd["launches"],
-                     "algorithmic_bytes_per_launch": kd["bytes"] / max(1, kd["launches"]),
-                     "algorithmic_flops_per_launch": kd["flops"] / max(1, kd["launches"])})
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "algorithmic_flops_per_launch": kd["flops"] / max(1, kd["launches"]),
+                     "traffic_over_algorithmic": (round(roofline["traffic"] / alg_bytes, 3)
+                                                  if roofline["traffic"] else None)})
     kernels = {}
     for k, v in kern.items():
         if v["launches"] == 0:
@@ -594,6 +631,8 @@ def main():
                       "TFLOP/s": round(v["flops"] / v["ms"] / 1e9, 2) if v["ms"] > 0 and v["flops"] else None}
 
     out_extra = {}
+    if graph_fig is not None:
+        out_extra["captured_cycles"] = graph_fig
     if tune is not None:
         out_extra["autotune"] = tune
     del x
@@ -688,6 +727,13 @@ def main():
             ms, gbs = time_dslash(P, torch, f, m0, P.PREC_NAMES[name])
             ds[name] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
             log(f"[bench] D at {name}: {ms:.4f} ms, {gbs:.0f} GB/s")
+        if nrhs > 1:
+            # one launch for all right-hand sides: each link read serves every RHS
+            ms, gbs = time_dslash(P, torch, f, m0, prec, nrhs=nrhs, reps=20)
+            ds[f"{wl['storage']}_x{nrhs}"] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                              "frac_hbm": round(gbs / HBM_PEAK_GBS, 3),
+                                              "bytes_per_site": (36 + 24 * nrhs) * P.PAIR_BYTES[prec]}
+            log(f"[bench] D at {wl['storage']} x {nrhs} RHS: {ms:.4f} ms, {gbs:.0f} GB/s")
         out_extra["dslash"] = ds
         out_extra["copy_GB/s"] = round(copy_bandwidth(torch), 1)
 
@@ -729,7 +775,7 @@ def main():
         "cycles": st0.cycles,
         "clean_restarts": st0.clean_restarts,
         "true_relres": st0.true_relres,
-        "true_relres_check": relres_check,
+        "true_relres_oracle": relres_oracle,
         "ms_per_step_without_event_timing": round(unprofiled_ms, 2),
         "p50_ms": round(lat_ms[len(lat_ms) // 2], 2),
         "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)], 2),

@@ -131,8 +131,18 @@ typedef struct sap_params {
  *              rotated v_{k+1}, so that D Z_k = V_{k+1} H^_k keeps holding up
  *              to the difference between the two residuals). In exact
  *              arithmetic nothing changes; it is meant for a low-precision
- *              basis (DW_SOLVE_V32). Other bits must be 0. */
-enum { DW_SOLVE_GRAPHS = 1, DW_SOLVE_V32 = 2, DW_SOLVE_INJECT = 4 };
+ *              basis (DW_SOLVE_V32, DW_SOLVE_A32).
+ *              DW_SOLVE_A32: the single-precision Arnoldi of Section 4.7:
+ *              V and Z stored in FP32, w = D z_j applied in FP32 (FP32 links
+ *              and arithmetic) and the Gram-Schmidt sweeps in FP32
+ *              arithmetic, so that almost all of the work is low precision;
+ *              the iterate, the explicit FP64 residual of every restart (in
+ *              c, and with DW_SOLVE_INJECT in G_{k+1} and v_{k+1}), the
+ *              small dense problems and the clean-restart test stay FP64.
+ *              With a low-precision SAP the column z_j is stored as
+ *              sigma M v_j (sigma the input scaling), which leaves the
+ *              iterate unchanged. Other bits must be 0. */
+enum { DW_SOLVE_GRAPHS = 1, DW_SOLVE_V32 = 2, DW_SOLVE_INJECT = 4, DW_SOLVE_A32 = 8 };
 
 typedef struct fgmresdr_params {
   int32_t m;
@@ -160,8 +170,10 @@ typedef struct dw_solve_stats {
 /* Thread-local text of the last error (never NULL). */
 const char* dw_last_error(void);
 
-/* Creates a context on HIP device `device`. `alloc` may be NULL (hipMalloc).
- * The allocator struct is copied. */
+/* Creates a context on HIP device `device`. `alloc` may be NULL (stream-
+ * ordered hipMallocAsync / hipFreeAsync). The allocator struct is copied.
+ * dw_ctx_destroy releases the caller's handle; fields created on the
+ * context keep it (and call its allocator) until they are destroyed. */
 dw_status dw_ctx_create(int32_t device, const dw_allocator* alloc, dw_ctx* out);
 dw_status dw_ctx_destroy(dw_ctx ctx);
 

@@ -14,9 +14,11 @@ with lattice extents L = (Lx, Ly, Lz, Lt).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import dataclasses
 import os
+import weakref
 
 import torch
 
@@ -29,7 +31,7 @@ __all__ = [
 
 DW_OK, DW_EINVAL, DW_ENOMEM, DW_EHIP, DW_ENOTCONV, DW_EBUSY, DW_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 DW_PREC_F64, DW_PREC_F32, DW_PREC_F16, DW_PREC_BF16 = 0, 1, 2, 3
-SOLVE_GRAPHS, SOLVE_V32, SOLVE_INJECT = 1, 2, 4
+SOLVE_GRAPHS, SOLVE_V32, SOLVE_INJECT, SOLVE_A32 = 1, 2, 4, 8
 PREC_NAMES = {"f64": DW_PREC_F64, "f32": DW_PREC_F32, "f16": DW_PREC_F16, "bf16": DW_PREC_BF16}
 PAIR_BYTES = {DW_PREC_F64: 16, DW_PREC_F32: 8, DW_PREC_F16: 4, DW_PREC_BF16: 4}
 
@@ -169,6 +171,21 @@ class SolveStats:
 
 _lib = None
 
+# Handles still open when the interpreter exits are closed before it tears
+# down (the library frees device memory through PyTorch's allocator, which
+# must still be alive then): servers first, then fields, then contexts.
+_live = {"server": weakref.WeakSet(), "field": weakref.WeakSet(), "context": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_all():
+    for kind in ("server", "field", "context"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
 
 def load(path: str = LIB_PATH):
     """Load libdwsap.so. Raises if it is missing: there is no fallback."""
@@ -273,6 +290,7 @@ class Context:
         _check(L.dw_ctx_create(device, ctypes.byref(self._alloc) if self._alloc else None, ctypes.byref(h)),
                "dw_ctx_create")
         self.handle = h
+        _live["context"].add(self)
 
     def profile(self, on: bool = True):
         """Per-kernel-class HIP-event timing of every launch made for this context."""
@@ -318,6 +336,7 @@ class Field:
         _check(lib().dw_field_create(ctx.handle, La, Ba, _dev_ptr(U), _stream(stream), ctypes.byref(h)),
                "dw_field_create")
         self.handle = h
+        _live["field"].add(self)
         self.volume = int(lib().dw_field_volume(h))
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
 
@@ -455,6 +474,7 @@ class Server:
         _check(lib().dw_server_create(ctx.handle, ctypes.byref(p), ctypes.byref(h)), "dw_server_create")
         self.ctx = ctx
         self.handle = h
+        _live["server"].add(self)
         self._live = {}
 
     @staticmethod

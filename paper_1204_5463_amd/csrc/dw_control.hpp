@@ -31,7 +31,15 @@ enum {
   kCClean = 13,   // clean restarts so far
   kCInject = 14,  // the injected v_{k+1} is used (Section 4.7)
   kCMaxIter = 15, // iteration limit
-  kCtl = 16
+  // the cycle just finished, kept when the next one opens (host accounting)
+  kCPrevInCycle = 16,
+  kCPrevJ0 = 17,
+  kCPrevJend = 18,
+  kCPrevFin = 19,
+  kCPrevDefl = 20,
+  kCPrevFresh = 21,
+  kCPrevInject = 22,
+  kCtl = 24
 };
 // double fields (kCtlD per right-hand side)
 enum { kDBnorm = 0, kDTolAbs = 1, kDResE = 2, kDResI = 3, kDRestartT = 4, kCtlD = 8 };

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -13,15 +14,27 @@
 #include "dw_geom.hpp"
 
 namespace dw {
+// Work tag of a launch inside a solver cycle: which right-hand sides it
+// covers and which gate decides whether it does work for each of them
+// (the kernels of a cycle are launched unconditionally and find their
+// gates on the device). kind >= 0: an Arnoldi step of that column.
+enum { kTagNone = -1, kTagFin = -2, kTagCycle = -3, kTagDefl = -4, kTagFresh = -5, kTagInject = -6 };
+struct ProfTagV {
+  int kind = kTagNone;
+  unsigned long long mask = 0;  // right-hand sides 0..63 covered by the launch
+};
+
 struct Profiler {
   struct Rec {
     int kc;
     hipEvent_t a, b;
     double bytes, flops;
+    ProfTagV tag;
   };
   std::mutex mu;
   bool on = false;
   std::vector<Rec> pending;
+  std::vector<Rec> held;  // finished tagged launches, awaiting the outcome of their cycle
   std::vector<hipEvent_t> pool;
   dw_kernel_stats acc[DW_K_COUNT] = {};
 };
@@ -32,6 +45,9 @@ struct dw_ctx_s {
   dw_allocator alloc;
   bool user_alloc;
   dw::Profiler prof;
+  // the caller's handle plus one per live field: a destroyed context stays
+  // until its last field is gone (the fields free through its allocator)
+  std::atomic<int> refs{1};
 };
 
 struct dw_field_s {
@@ -47,6 +63,9 @@ struct dw_field_s {
 };
 
 namespace dw {
+
+// drops one reference of a context, deleting it with the last one
+void ctx_release(dw_ctx ctx);
 
 // ---- errors -----------------------------------------------------------------
 void set_error(const char* fmt, ...);
@@ -92,8 +111,46 @@ struct KTimer {
   KTimer(int kclass, hipStream_t stream);
   void done(double bytes, double flops);
 };
-// resolves finished timing records (of the calling thread's profiler if null)
+// resolves finished timing records (of the calling thread's profiler if null);
+// tagged records wait in `held` for prof_resolve
 void prof_flush(Profiler* p = nullptr);
+// sets the work tag of the calling thread's following launches
+struct ProfTag {
+  ProfTagV prev;
+  ProfTag(int kind, unsigned long long mask);
+  ~ProfTag();
+};
+// Accounts the held records of a finished cycle: active(kind, r) says
+// whether right-hand side r did work under that tag; a launch counts with
+// the fraction of its right-hand sides that did, and one that did none
+// (every gate closed) is not counted at all.
+Profiler* prof_current();
+template <typename F>
+void prof_resolve(F&& active) {
+  Profiler* p = prof_current();
+  if (!p) return;
+  prof_flush(p);
+  std::lock_guard<std::mutex> lk(p->mu);
+  for (auto& r : p->held) {
+    int n = 0, on = 0;
+    for (int i = 0; i < 64; ++i)
+      if ((r.tag.mask >> i) & 1ull) {
+        ++n;
+        if (active(r.tag.kind, i)) ++on;
+      }
+    float ms = 0.f;
+    if (on > 0 && n > 0 && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      dw_kernel_stats& k = p->acc[r.kc];
+      k.launches += 1;
+      k.ms += ms;
+      k.bytes += r.bytes * on / n;
+      k.flops += r.flops * on / n;
+    }
+    p->pool.push_back(r.a);
+    p->pool.push_back(r.b);
+  }
+  p->held.clear();
+}
 
 // ---- device memory ------------------------------------------------------------
 void* dev_alloc(dw_ctx ctx, size_t bytes, hipStream_t stream);
@@ -166,6 +223,11 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
                               const double* dmass = nullptr);
 dw_status launch_dslash_lowp(const Geom& g, double m0, int prec, const void* x, const void* U, void* y, int nrhs,
                              hipStream_t s, const void* C = nullptr);
+// w = D z with FP32 vectors, FP32 links (and clover term) and FP32 arithmetic:
+// the operator of the single-precision Arnoldi; mass from dmass (device)
+dw_status launch_dslash_a32(const Geom& g, const void* x, const void* U32, void* y, int nrhs, long long xs,
+                            long long ys, hipStream_t s, const int* rlist, const void* C32, const int* gate, int gstride,
+                            const double* dmass);
 
 // One SAP colour sweep: for every block of `colour`, r = v - D z on the
 // block, nmr MR steps on D^l y = r, z += y. v at storage precision `prec`,

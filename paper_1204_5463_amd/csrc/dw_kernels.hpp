@@ -40,18 +40,21 @@ dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const doub
 // nv final columns; u or w may be null. partials: (2 kMaxM + 5) * kBlasGrid pairs.
 // V and u are stored at prec_v (FP64 or FP32), w is FP64.
 // dcol (may be null): finalise column *dcol (u = V_{*dcol}, nv = *dcol <= nv)
-dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const double* w, long long n,
+// prec_w: storage of w, FP64, or FP32 with an FP32 basis: then the sweep's
+// arithmetic is FP32 too (the single-precision Arnoldi), its per-workgroup
+// sums combined in FP64
+dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const void* w, long long n,
                     double* partials, double* out, hipStream_t s, const int* gate = nullptr,
-                    const int* dcol = nullptr);
+                    const int* dcol = nullptr, int prec_w = DW_PREC_F64);
 // gs_update: jcol >= 0: V_jcol <- (V_jcol - V a)/beta; w != null:
 // wout <- w - V b - c V_jcol (c only if jcol >= 0), nrm2 <- ||wout||^2.
 // coef as written by dense_gs_coef.
 // V and wout are stored at prec_v (FP64 or FP32); with FP32 storage nrm2 is
 // the squared norm of the stored (rounded) wout.
-// dcol (may be null): nv = jcol = *dcol
-dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const double* w, void* wout,
+// dcol (may be null): nv = jcol = *dcol; prec_w as for gs_reduce
+dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const void* w, void* wout,
                     const double* coef, long long n, double* partials, double* nrm2, hipStream_t s,
-                    const int* gate = nullptr, const int* dcol = nullptr);
+                    const int* gate = nullptr, const int* dcol = nullptr, int prec_w = DW_PREC_F64);
 
 // ---- small dense FP64 (one workgroup) ---------------------------------------------
 // Scalars block written by dense_step / dense_cycle_end (doubles):

@@ -194,10 +194,12 @@ __global__ void __launch_bounds__(kThreads)
 // one update sweep forms v = (u - V a) / beta and w' = w - V b - c v.
 // Partial-sum slots: [0, nv) a, [nv, 2 nv) b, 2 nv: u^H u, 2 nv + 1: u^H w,
 // 2 nv + 2: w^H w.
-template <bool HU, bool HW, typename SV>
+// SW: storage of w; T: arithmetic (double, or float for the single-precision
+// Arnoldi); the per-workgroup sums are combined in double.
+template <bool HU, bool HW, typename SV, typename SW, typename T>
 __global__ void __launch_bounds__(kThreads)
     k_gs_reduce(const SV* __restrict__ V, long long stride, int c0, int nc, int nv, const SV* __restrict__ u,
-                const s64* __restrict__ w, long long n, int first, s64* __restrict__ partials,
+                const SW* __restrict__ w, long long n, int first, s64* __restrict__ partials,
                 const int* __restrict__ gate, const int* __restrict__ dcol, int chunk) {
   constexpr int NA = kGsCols;
   if (gate && *gate == 0) return;
@@ -214,21 +216,21 @@ __global__ void __launch_bounds__(kThreads)
     first = chunk == 0;
   }
   __shared__ double red[kThreads / kWave][2 * NA + 3][2];
-  cplx<double> au[NA], aw[NA], uu = mk(0.0, 0.0), uw = mk(0.0, 0.0), ww = mk(0.0, 0.0);
+  cplx<T> au[NA], aw[NA], uu = mk<T>(0, 0), uw = mk<T>(0, 0), ww = mk<T>(0, 0);
 #pragma unroll
   for (int c = 0; c < NA; ++c) {
-    au[c] = mk(0.0, 0.0);
-    aw[c] = mk(0.0, 0.0);
+    au[c] = mk<T>(0, 0);
+    aw[c] = mk<T>(0, 0);
   }
   const long long step = (long long)gridDim.x * kThreads;
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) {
-    cplx<double> uv = mk(0.0, 0.0), wv = mk(0.0, 0.0);
-    if constexpr (HU) uv = ld<double>(u + i);
-    if constexpr (HW) wv = ld<double>(w + i);
+    cplx<T> uv = mk<T>(0, 0), wv = mk<T>(0, 0);
+    if constexpr (HU) uv = ld<T>(u + i);
+    if constexpr (HW) wv = ld<T>(w + i);
 #pragma unroll
     for (int c = 0; c < NA; ++c)
       if (c < nc) {
-        const cplx<double> vc = ld<double>(V + (long long)(c0 + c) * stride + i);
+        const cplx<T> vc = ld<T>(V + (long long)(c0 + c) * stride + i);
         if constexpr (HU) au[c] += cdot(vc, uv);
         if constexpr (HW) aw[c] += cdot(vc, wv);
       }
@@ -239,8 +241,8 @@ __global__ void __launch_bounds__(kThreads)
     }
   }
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  auto put = [&](int slot, cplx<double> v) {
-    const double re = wsum(v.re), im = wsum(v.im);
+  auto put = [&](int slot, cplx<T> v) {
+    const double re = wsum((double)v.re), im = wsum((double)v.im);
     if (lane == 0) {
       red[wave][slot][0] = re;
       red[wave][slot][1] = im;
@@ -280,35 +282,35 @@ __global__ void __launch_bounds__(kThreads)
 // coef: a[0..nv), b[0..nv), c (slot 2 nv), 1/beta (slot 2 nv + 1, real part).
 // HU: V_jcol <- (V_jcol - V a) / beta (in place); HW: wout <- w - V b - c V_jcol,
 // partials[block] = sum |wout|^2 over the block's elements.
-template <bool HU, bool HW, typename SV>
+template <bool HU, bool HW, typename SV, typename SW, typename T>
 __global__ void __launch_bounds__(kThreads)
-    k_gs_update(SV* __restrict__ V, long long stride, int nv, int jcol, const s64* __restrict__ w,
+    k_gs_update(SV* __restrict__ V, long long stride, int nv, int jcol, const SW* __restrict__ w,
                 SV* __restrict__ wout, const s64* __restrict__ coef, long long n, s64* __restrict__ partials,
                 const int* __restrict__ gate, const int* __restrict__ dcol) {
   if (gate && *gate == 0) return;
   if (dcol) nv = jcol = *dcol;
-  __shared__ cplx<double> ca[kMaxM + 1], cb[kMaxM + 1];
+  __shared__ cplx<T> ca[kMaxM + 1], cb[kMaxM + 1];
   __shared__ double red[kThreads / kWave];
   for (int c = threadIdx.x; c < nv; c += kThreads) {
-    ca[c] = ld<double>(coef + c);
-    cb[c] = ld<double>(coef + nv + c);
+    ca[c] = ld<T>(coef + c);
+    cb[c] = ld<T>(coef + nv + c);
   }
   __syncthreads();
-  const cplx<double> cj = ld<double>(coef + 2 * nv);
-  const double invbeta = coef[2 * nv + 1].x;
+  const cplx<T> cj = ld<T>(coef + 2 * nv);
+  const T invbeta = (T)coef[2 * nv + 1].x;
   double nrm = 0;
   const long long step = (long long)gridDim.x * kThreads;
   for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += step) {
-    cplx<double> uu = mk(0.0, 0.0), wa = mk(0.0, 0.0);
-    if constexpr (HU) uu = ld<double>(V + (long long)jcol * stride + i);
-    if constexpr (HW) wa = ld<double>(w + i);
+    cplx<T> uu = mk<T>(0, 0), wa = mk<T>(0, 0);
+    if constexpr (HU) uu = ld<T>(V + (long long)jcol * stride + i);
+    if constexpr (HW) wa = ld<T>(w + i);
     // columns in groups of kUpd with all loads of a group issued together,
     // so that each thread keeps several HBM reads in flight
     int c = 0;
     for (; c + kUpd <= nv; c += kUpd) {
-      cplx<double> vc[kUpd];
+      cplx<T> vc[kUpd];
 #pragma unroll
-      for (int q = 0; q < kUpd; ++q) vc[q] = ld<double>(V + (long long)(c + q) * stride + i);
+      for (int q = 0; q < kUpd; ++q) vc[q] = ld<T>(V + (long long)(c + q) * stride + i);
 #pragma unroll
       for (int q = 0; q < kUpd; ++q) {
         if constexpr (HU) uu -= ca[c + q] * vc[q];
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(kThreads)
       }
     }
     for (; c < nv; ++c) {
-      const cplx<double> vc = ld<double>(V + (long long)c * stride + i);
+      const cplx<T> vc = ld<T>(V + (long long)c * stride + i);
       if constexpr (HU) uu -= ca[c] * vc;
       if constexpr (HW) wa -= cb[c] * vc;
     }
@@ -327,8 +329,8 @@ __global__ void __launch_bounds__(kThreads)
     }
     if constexpr (HW) {
       st(wout + i, wa);
-      if constexpr (std::is_same<SV, s64>::value) nrm += norm2(wa);
-      else nrm += norm2(ld<double>(wout + i));  // the stored, rounded vector
+      if constexpr (sizeof(SV) == 2 * sizeof(T)) nrm += (double)norm2(wa);  // stored without rounding
+      else nrm += norm2(ld<double>(wout + i));                               // the stored, rounded vector
     }
   }
   if constexpr (HW) {
@@ -442,8 +444,8 @@ dw_status blas_rotate(int prec_v, void* V, long long stride, int nin, const doub
 
 namespace dw {
 
-template <typename SV>
-dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, const s64* wp, long long n,
+template <typename SV, typename SW, typename T>
+dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, const SW* wp, long long n,
                       double* partials, double* out, hipStream_t s, const int* gate, const int* dcol) {
   const bool hu = up != nullptr || dcol != nullptr, hw = wp != nullptr;
   const unsigned G = grid_for(n);
@@ -458,16 +460,16 @@ dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, cons
     KTimer kt(DW_K_DOTS, s);
     s64* part = (s64*)partials;
     if (hu && hw)
-      hipLaunchKernelGGL((k_gs_reduce<true, true, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0,
+      hipLaunchKernelGGL((k_gs_reduce<true, true, SV, SW, T>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n, q == 0,
                          part, gate, dcol, q);
     else if (hu)
-      hipLaunchKernelGGL((k_gs_reduce<true, false, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
+      hipLaunchKernelGGL((k_gs_reduce<true, false, SV, SW, T>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
                          q == 0, part, gate, dcol, q);
     else
-      hipLaunchKernelGGL((k_gs_reduce<false, true, SV>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
+      hipLaunchKernelGGL((k_gs_reduce<false, true, SV, SW, T>), G, kThreads, 0, s, Vp, stride, c0, nc, nv, up, wp, n,
                          q == 0, part, gate, dcol, q);
     DW_CHECK_LAUNCH();
-    kt.done((double)n * (sizeof(SV) * (nc + (hu ? 1 : 0)) + (hw ? 16 : 0)),
+    kt.done((double)n * (sizeof(SV) * (nc + (hu ? 1 : 0)) + (hw ? sizeof(SW) : 0)),
             (double)n * 8 * nc * ((hu ? 1 : 0) + (hw ? 1 : 0)));
   }
   KTimer kr(DW_K_REDUCE, s);
@@ -478,34 +480,40 @@ dw_status gs_reduce_t(const SV* Vp, long long stride, int nv, const SV* up, cons
   return DW_OK;
 }
 
-dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const double* w, long long n,
-                    double* partials, double* out, hipStream_t s, const int* gate, const int* dcol) {
-  if (nv < 0 || nv > kMaxM + 1 || (!u && !w && !dcol) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
+dw_status gs_reduce(int prec_v, const void* V, long long stride, int nv, const void* u, const void* w, long long n,
+                    double* partials, double* out, hipStream_t s, const int* gate, const int* dcol, int prec_w) {
+  if (nv < 0 || nv > kMaxM + 1 || (!u && !w && !dcol) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32) ||
+      (prec_w == DW_PREC_F32 && prec_v != DW_PREC_F32) || (prec_w != DW_PREC_F64 && prec_w != DW_PREC_F32)) {
     set_error("gs_reduce: bad arguments");
     return DW_EINVAL;
   }
+  if (prec_w == DW_PREC_F32)
+    return gs_reduce_t<s32, s32, float>((const s32*)V, stride, nv, (const s32*)u, (const s32*)w, n, partials, out, s,
+                                        gate, dcol);
   if (prec_v == DW_PREC_F64)
-    return gs_reduce_t((const s64*)V, stride, nv, (const s64*)u, (const s64*)w, n, partials, out, s, gate, dcol);
-  return gs_reduce_t((const s32*)V, stride, nv, (const s32*)u, (const s64*)w, n, partials, out, s, gate, dcol);
+    return gs_reduce_t<s64, s64, double>((const s64*)V, stride, nv, (const s64*)u, (const s64*)w, n, partials, out,
+                                         s, gate, dcol);
+  return gs_reduce_t<s32, s64, double>((const s32*)V, stride, nv, (const s32*)u, (const s64*)w, n, partials, out, s,
+                                       gate, dcol);
 }
 
-template <typename SV>
-dw_status gs_update_t(SV* Vp, long long stride, int nv, int jcol, const s64* w, SV* wout, const double* coef,
+template <typename SV, typename SW, typename T>
+dw_status gs_update_t(SV* Vp, long long stride, int nv, int jcol, const SW* w, SV* wout, const double* coef,
                       long long n, double* partials, double* nrm2, hipStream_t s, const int* gate, const int* dcol) {
   const bool hu = jcol >= 0 || dcol != nullptr, hw = w != nullptr;
   const unsigned G = grid_for(n);
   KTimer kt(DW_K_SUBCOLS, s);
   if (hu && hw)
-    hipLaunchKernelGGL((k_gs_update<true, true, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
+    hipLaunchKernelGGL((k_gs_update<true, true, SV, SW, T>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
                        (const s64*)coef, n, (s64*)partials, gate, dcol);
   else if (hu)
-    hipLaunchKernelGGL((k_gs_update<true, false, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
+    hipLaunchKernelGGL((k_gs_update<true, false, SV, SW, T>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
                        (const s64*)coef, n, (s64*)partials, gate, dcol);
   else
-    hipLaunchKernelGGL((k_gs_update<false, true, SV>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
+    hipLaunchKernelGGL((k_gs_update<false, true, SV, SW, T>), G, kThreads, 0, s, Vp, stride, nv, jcol, w, wout,
                        (const s64*)coef, n, (s64*)partials, gate, dcol);
   DW_CHECK_LAUNCH();
-  kt.done((double)n * (sizeof(SV) * (nv + (hu ? 2 : 0) + (hw ? 1 : 0)) + (hw ? 16 : 0)),
+  kt.done((double)n * (sizeof(SV) * (nv + (hu ? 2 : 0) + (hw ? 1 : 0)) + (hw ? sizeof(SW) : 0)),
           (double)n * 8 * nv * ((hu ? 1 : 0) + (hw ? 1 : 0)));
   if (hw) {
     KTimer kr(DW_K_REDUCE, s);
@@ -517,16 +525,22 @@ dw_status gs_update_t(SV* Vp, long long stride, int nv, int jcol, const s64* w, 
   return DW_OK;
 }
 
-dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const double* w, void* wout,
+dw_status gs_update(int prec_v, void* V, long long stride, int nv, int jcol, const void* w, void* wout,
                     const double* coef, long long n, double* partials, double* nrm2, hipStream_t s, const int* gate,
-                    const int* dcol) {
-  if (nv < 0 || nv > kMaxM + 1 || (jcol < 0 && !w && !dcol) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32)) {
+                    const int* dcol, int prec_w) {
+  if (nv < 0 || nv > kMaxM + 1 || (jcol < 0 && !w && !dcol) || (prec_v != DW_PREC_F64 && prec_v != DW_PREC_F32) ||
+      (prec_w == DW_PREC_F32 && prec_v != DW_PREC_F32) || (prec_w != DW_PREC_F64 && prec_w != DW_PREC_F32)) {
     set_error("gs_update: bad arguments");
     return DW_EINVAL;
   }
+  if (prec_w == DW_PREC_F32)
+    return gs_update_t<s32, s32, float>((s32*)V, stride, nv, jcol, (const s32*)w, (s32*)wout, coef, n, partials,
+                                        nrm2, s, gate, dcol);
   if (prec_v == DW_PREC_F64)
-    return gs_update_t((s64*)V, stride, nv, jcol, (const s64*)w, (s64*)wout, coef, n, partials, nrm2, s, gate, dcol);
-  return gs_update_t((s32*)V, stride, nv, jcol, (const s64*)w, (s32*)wout, coef, n, partials, nrm2, s, gate, dcol);
+    return gs_update_t<s64, s64, double>((s64*)V, stride, nv, jcol, (const s64*)w, (s64*)wout, coef, n, partials,
+                                         nrm2, s, gate, dcol);
+  return gs_update_t<s32, s64, double>((s32*)V, stride, nv, jcol, (const s64*)w, (s32*)wout, coef, n, partials,
+                                       nrm2, s, gate, dcol);
 }
 
 }  // namespace dw

@@ -90,6 +90,13 @@ __global__ void k_ctl_next(int* __restrict__ ctl, int nr, int m, int k) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nr) return;
   int* c = ctl + r * kCtl;
+  c[kCPrevInCycle] = c[kCInCycle];
+  c[kCPrevJ0] = c[kCJ0];
+  c[kCPrevJend] = c[kCJend];
+  c[kCPrevFin] = c[kCFin];
+  c[kCPrevDefl] = c[kCDefl];
+  c[kCPrevFresh] = c[kCFresh];
+  c[kCPrevInject] = c[kCInject];
   const int live = c[kCDone] ? 0 : 1;
   const int j0 = c[kCDefl] ? k : 0;
   c[kCJ0] = j0;

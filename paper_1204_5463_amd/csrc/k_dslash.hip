@@ -115,8 +115,9 @@ __global__ void __launch_bounds__(MAXT)
   // same links run together on one XCD
   const int wi = xcd_remap(blockIdx.x, g.nblk * nr);
   if (wi < 0) return;  // uniform for the workgroup
-  const int b = wi / nr;
-  const int rhs = rlist ? rlist[wi - b * nr] : wi - b * nr;
+  const int bi = wi / nr;
+  const int b = tiled_block(g, bi);
+  const int rhs = rlist ? rlist[wi - bi * nr] : wi - bi * nr;
   if (dc.gate && dc.gate[(long long)rhs * dc.gstride] == 0) return;  // uniform for the workgroup
   if (dc.dmass) diag = (T)(4.0 + *dc.dmass);
   const int l = threadIdx.x;
@@ -300,6 +301,22 @@ dw_status launch_dslash_outer(const Geom& g, double m0, int prec_x, const void* 
   kt.done((double)g.V * nrhs *
               (12.0 * pair_bytes(prec_x) + 36 * 16 + 12 * 16 + (mode == 1 ? 12 * 16 : 0) + (Cg ? kCloverPairs * 16 : 0)),
           (double)g.V * nrhs * (kFlopsPerSite + (Cg ? kCloverFlops : 0.0)));
+  return DW_OK;
+}
+
+dw_status launch_dslash_a32(const Geom& g, const void* x, const void* U32, void* y, int nrhs, long long xs,
+                            long long ys, hipStream_t s, const int* rlist, const void* C32, const int* gate, int gstride,
+                            const double* dmass) {
+  if (nrhs < 1) return DW_OK;
+  DCtl dc;
+  dc.gate = gate;
+  dc.gstride = gstride;
+  dc.dmass = dmass;
+  KTimer kt(DW_K_DSLASH_LOWP, s);
+  DW_TRY((launch_c<float, s32, s32, s32, 0>(g, 4.0f, (const s32*)x, 1.0f, (const s32*)U32, (s32*)y, nullptr, xs, ys,
+                                             nrhs, rlist, s, (const s32*)C32, dc)));
+  kt.done((double)g.V * nrhs * (60.0 * 8 + (C32 ? kCloverPairs * 8 : 0)),
+          (double)g.V * nrhs * (kFlopsPerSite + (C32 ? kCloverFlops : 0.0)));
   return DW_OK;
 }
 

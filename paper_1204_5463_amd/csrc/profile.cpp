@@ -6,6 +6,15 @@
 namespace dw {
 
 static thread_local Profiler* t_prof = nullptr;
+static thread_local ProfTagV t_tag;
+
+Profiler* prof_current() { return t_prof; }
+
+ProfTag::ProfTag(int kind, unsigned long long mask) : prev(t_tag) {
+  t_tag.kind = kind;
+  t_tag.mask = mask;
+}
+ProfTag::~ProfTag() { t_tag = prev; }
 
 ProfScope::ProfScope(dw_ctx ctx) : prev(t_prof) { t_prof = (ctx && ctx->prof.on) ? &ctx->prof : nullptr; }
 ProfScope::~ProfScope() {
@@ -41,7 +50,7 @@ void KTimer::done(double bytes, double flops) {
     if (b) p->pool.push_back(b);
     return;
   }
-  p->pending.push_back(Profiler::Rec{kc, a, b, bytes, flops});
+  p->pending.push_back(Profiler::Rec{kc, a, b, bytes, flops, t_tag});
   p = nullptr;
 }
 
@@ -53,6 +62,10 @@ void prof_flush(Profiler* p) {
   for (auto& r : p->pending) {
     if (hipEventQuery(r.b) != hipSuccess) {
       keep.push_back(r);
+      continue;
+    }
+    if (r.tag.kind != kTagNone) {
+      p->held.push_back(r);
       continue;
     }
     float ms = 0.f;

@@ -33,6 +33,10 @@ void clear_error() { g_last_error.clear(); }
 // Without a caller allocator, memory is stream-ordered (hipMallocAsync /
 // hipFreeAsync on the call's stream), so that freeing a temporary at the end
 // of an asynchronous call does not synchronise the device.
+void ctx_release(dw_ctx ctx) {
+  if (ctx->refs.fetch_sub(1) == 1) delete ctx;
+}
+
 void* dev_alloc(dw_ctx ctx, size_t bytes, hipStream_t stream) {
   if (ctx->user_alloc) return ctx->alloc.alloc(bytes, stream, ctx->alloc.user);
   void* p = nullptr;
@@ -139,7 +143,7 @@ dw_status dw_ctx_create(int32_t device, const dw_allocator* alloc, dw_ctx* out) 
 
 dw_status dw_ctx_destroy(dw_ctx ctx) {
   clear_error();
-  delete ctx;
+  if (ctx) ctx_release(ctx);
   return DW_OK;
 }
 
@@ -186,6 +190,7 @@ dw_status dw_field_create(dw_ctx ctx, const int32_t L[4], const int32_t block[4]
       return st;
     }
   }
+  ctx->refs.fetch_add(1);
   *out = f;
   return DW_OK;
 }
@@ -198,7 +203,9 @@ dw_status dw_field_destroy(dw_field f) {
     dev_free(f->ctx, f->U[p], f->stream);
     dev_free(f->ctx, f->C[p], f->stream);
   }
+  dw_ctx ctx = f->ctx;
   delete f;
+  ctx_release(ctx);
   return DW_OK;
 }
 

@@ -61,6 +61,13 @@ using namespace dw;
 namespace {
 
 constexpr double kBdTol = 1e-14;  // breakdown: h_{j+1,j} <= kBdTol ||H^||
+constexpr int kMaxBatch = 64;     // right-hand sides of one lock-step batch
+
+unsigned long long rhs_mask(const std::vector<int>& rs) {
+  unsigned long long m = 0;
+  for (int r : rs) m |= 1ull << r;
+  return m;
+}
 
 // One cycle shape: which right-hand sides take part and from which column
 // (state 0: stopped, 1: fresh start at column 0, 2: deflated start at k),
@@ -93,10 +100,15 @@ struct Work {
     if (ctld_h) (void)hipHostFree(ctld_h);
   }
   int vprec = DW_PREC_F64;  // storage of the Krylov basis V
+  int zstore = DW_PREC_F64; // storage of the preconditioned basis Z
+  bool a32 = false;         // single-precision Arnoldi (w = D z and Gram-Schmidt in FP32)
   // basis of RHS r, and its column j
   void* Vr(int r) const { return (char*)V.p + (size_t)r * (m + 1) * n * pair_bytes(vprec); }
   void* Vc(int r, int j) const { return (char*)Vr(r) + (size_t)j * n * pair_bytes(vprec); }
-  double* Zr(int r) const { return Z.as<double>() + 2 * (long long)r * m * n; }
+  void* Zr(int r) const { return (char*)Z.p + (size_t)r * m * n * pair_bytes(zstore); }
+  void* Zc(int r, int j) const { return (char*)Zr(r) + (size_t)j * n * pair_bytes(zstore); }
+  // w of RHS r at the Arnoldi's precision (the buffer holds FP64 pairs)
+  void* wr(int r) const { return (char*)w.p + (size_t)r * n * (a32 ? 8 : 16); }
   double* vec(const DevBuf& d, int r) const { return d.as<double>() + 2 * (long long)r * n; }
   double* Hr(int r) const { return H.as<double>() + 2 * (long long)r * kLd * kMaxM; }
   double* cr(int r) const { return c.as<double>() + 2 * (long long)r * kLd; }
@@ -120,12 +132,19 @@ struct Work {
   double* injr(int r) const { return inj.as<double>() + 2 * (long long)r * (2 * kLd + 4); }
 };
 
-int basis_prec(const fgmresdr_params* P) { return (P->flags & DW_SOLVE_V32) ? DW_PREC_F32 : DW_PREC_F64; }
+int basis_prec(const fgmresdr_params* P) {
+  return (P->flags & (DW_SOLVE_V32 | DW_SOLVE_A32)) ? DW_PREC_F32 : DW_PREC_F64;
+}
+int zstore_prec(const fgmresdr_params* P) { return (P->flags & DW_SOLVE_A32) ? DW_PREC_F32 : DW_PREC_F64; }
 
-size_t bytes_per_rhs(long long n, int m, int prec, int vprec) {
+// the SAP accumulator goes straight into Z when they share the precision
+bool sap_into_z(int prec, int zstore) { return (prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32) == zstore; }
+
+size_t bytes_per_rhs(long long n, int m, int prec, int vprec, int zstore) {
   const int zprec = prec == DW_PREC_F64 ? DW_PREC_F64 : DW_PREC_F32;
-  return (size_t)n * pair_bytes(vprec) * (m + 1) + (size_t)n * 16 * (m + 4) + (size_t)n * pair_bytes(prec) +
-         (zprec != DW_PREC_F64 ? (size_t)n * pair_bytes(zprec) : 0) + (size_t)(2 * kLd + 6) * kBlasGrid * 16;
+  return (size_t)n * pair_bytes(vprec) * (m + 1) + (size_t)n * pair_bytes(zstore) * m + (size_t)n * 16 * 4 +
+         (size_t)n * pair_bytes(prec) + (sap_into_z(prec, zstore) ? 0 : (size_t)n * pair_bytes(zprec)) +
+         (size_t)(2 * kLd + 6) * kBlasGrid * 16;
 }
 
 dw_status alloc_work(dw_field f, const fgmresdr_params* P, int nr, Work& W, hipStream_t s) {
@@ -141,9 +160,11 @@ dw_status alloc_work(dw_field f, const fgmresdr_params* P, int nr, Work& W, hipS
   W.clover[0] = f->C[prec];
   W.clover[1] = f->C[DW_PREC_F64];
   W.vprec = basis_prec(P);
+  W.zstore = zstore_prec(P);
+  W.a32 = (P->flags & DW_SOLVE_A32) != 0;
   DW_TRY(W.V.alloc(ctx, (size_t)nr * (P->m + 1) * n * pair_bytes(W.vprec), s));
-  DW_TRY(W.Z.alloc(ctx, (size_t)nr * P->m * n * 16, s));
-  if (zprec != DW_PREC_F64) DW_TRY(W.zs.alloc(ctx, (size_t)nr * n * pair_bytes(zprec), s));
+  DW_TRY(W.Z.alloc(ctx, (size_t)nr * P->m * n * pair_bytes(W.zstore), s));
+  if (!sap_into_z(prec, W.zstore)) DW_TRY(W.zs.alloc(ctx, (size_t)nr * n * pair_bytes(zprec), s));
   DW_TRY(W.w.alloc(ctx, (size_t)nr * n * 16, s));
   DW_TRY(W.r.alloc(ctx, (size_t)nr * n * 16, s));
   DW_TRY(W.x.alloc(ctx, (size_t)nr * n * 16, s));
@@ -198,10 +219,11 @@ struct Solver {
   // Restart preparation for every right-hand side in `rs` whose record asks
   // for a fresh start: H^ = 0, c = beta e_1, v_1 = r / beta. Then the
   // records open the next cycle.
-  dw_status fresh_and_open(const std::vector<int>& rs) {
+  dw_status fresh_and_open(const std::vector<int>& rs, bool in_cycle = true) {
     const long long n = W.n;
     for (int r : rs) {
       const int* g = W.gate(r, kCFresh);
+      ProfTag tag_f(in_cycle ? kTagFresh : kTagNone, 1ull << r);
       DW_TRY(dense_fresh(W.Hr(r), W.cr(r), W.nrmr(r), W.scalr(r), s, g));
       if (W.vprec == DW_PREC_F64)
         DW_TRY(blas_scale(W.vec(W.r, r), (double*)W.Vr(r), W.scalr(r) + kSclBetaInv, n, s, g));
@@ -227,7 +249,7 @@ struct Solver {
     DW_TRY(copy_doubles(W.b.as<double>(), W.r.as<double>(), 2 * (long long)nr * n, nullptr, s));
     DW_TRY(ctl_init(W.ctl.as<int>(), W.ctld.as<double>(), W.nrm.as<double>(), 2, nr, P->tol, P->restart_t,
                     P->max_iter, s));
-    return fresh_and_open(all);
+    return fresh_and_open(all, false);
   }
 
   dw_status upload_lists(Shape& sh) {
@@ -254,6 +276,7 @@ struct Solver {
     const long long n = W.n;
     const int m = W.m, k = W.k, nr = W.nr;
     const bool inject = (P->flags & DW_SOLVE_INJECT) != 0;
+    const int wprec = W.a32 ? DW_PREC_F32 : DW_PREC_F64;
     const double* mass = W.mass.as<double>();
     const int* gate_live = W.ctl.as<int>() + kCLive;
     const int* gate_cyc = W.ctl.as<int>() + kCInCycle;
@@ -273,38 +296,55 @@ struct Solver {
         if (j0_of(r) <= j) part.push_back(r);
       const int np = (int)part.size();
       const int* rl = sh.rl.as<int>() + (size_t)j * nr;
+      ProfTag tag_step(j, rhs_mask(part));
       // z_j = M_j applied to sigma * v_j (lagged vectors scaled by their
       // provisional norm; any z_j keeps A Z = V H^ exact in FGMRES)
-      for (int r : part)
+      for (int r : part) {
+        ProfTag tag_rhs(j, 1ull << r);
         DW_TRY(launch_convert(W.vprec, W.Vc(r, j), prec, (char*)W.vs.p + (size_t)r * n * pair_bytes(prec), sigma, n,
                               s, j > j0_of(r) ? W.scalr(r) + kSclHinv : nullptr, W.gate(r, kCLive)));
-      void* zacc = zprec == DW_PREC_F64 ? (void*)(W.Z.as<double>() + 2 * (long long)j * n) : W.zs.p;
-      const long long zstride = zprec == DW_PREC_F64 ? (long long)m * n : n;
+      }
+      // the accumulator is column j of Z itself when they share the
+      // precision; with the low-precision SAP into an FP32 Z the column is
+      // sigma M v_j, a scaled flexible preconditioner (A Z = V H^ holds for
+      // the stored Z, and x = x0 + Z eta is unchanged)
+      const bool direct = sap_into_z(prec, W.zstore);
+      void* zacc = direct ? W.Zc(0, j) : W.zs.p;
+      const long long zstride = direct ? (long long)m * n : n;
       for (int cy = 0; cy < P->sap.ncycles; ++cy)
         for (int colour = 0; colour < 2; ++colour)
           DW_TRY(launch_sap_colour(g, 0.0, prec, W.vs.p, zacc, f->U[prec], colour, P->sap.nmr,
                                    cy == 0 && colour == 0 ? 1 : 0, np, n, zstride, s, rl, f->C[prec],
                                    P->sap.mr_reduction, gate_live, kCtl, mass));
-      if (zprec != DW_PREC_F64)
-        for (int r : part)
-          DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), DW_PREC_F64,
-                                W.Zr(r) + 2 * (long long)j * n, 1.0 / sigma, n, s, nullptr, W.gate(r, kCLive)));
-      // w = D z_j in FP64 on the stored z_j, all participants in one launch
-      DW_TRY(launch_dslash_outer(g, 0.0, DW_PREC_F64, W.Z.as<double>() + 2 * (long long)j * n, 1.0,
-                                 f->U[DW_PREC_F64], W.w.as<double>(), nullptr, 0, np, (long long)m * n, n, s, rl,
-                                 f->C[DW_PREC_F64], gate_live, kCtl, mass));
+      if (!direct)
+        for (int r : part) {
+          ProfTag tag_rhs(j, 1ull << r);
+          DW_TRY(launch_convert(zprec, (char*)W.zs.p + (size_t)r * n * pair_bytes(zprec), W.zstore, W.Zc(r, j),
+                                1.0 / sigma, n, s, nullptr, W.gate(r, kCLive)));
+        }
+      // w = D z_j on the stored z_j, all participants in one launch: FP64,
+      // so that A Z = V H^ holds to FP64 accuracy whatever precision Z has,
+      // or FP32 (links, arithmetic and w) in the single-precision Arnoldi
+      if (W.a32)
+        DW_TRY(launch_dslash_a32(g, W.Zc(0, j), f->U[DW_PREC_F32], W.w.p, np, (long long)m * n, n, s, rl,
+                                 f->C[DW_PREC_F32], gate_live, kCtl, mass));
+      else
+        DW_TRY(launch_dslash_outer(g, 0.0, DW_PREC_F64, W.Zc(0, j), 1.0, f->U[DW_PREC_F64], W.w.as<double>(),
+                                   nullptr, 0, np, (long long)m * n, n, s, rl, f->C[DW_PREC_F64], gate_live, kCtl,
+                                   mass));
       // Gram-Schmidt with delayed reorthogonalisation, per right-hand side
       for (int r : part) {
+        ProfTag tag_rhs(j, 1ull << r);
         const bool lagged = j > j0_of(r);
         const int* gl = W.gate(r, kCLive);
         void* V = W.Vr(r);
         const int nv = lagged ? j : j + 1;
-        DW_TRY(gs_reduce(W.vprec, V, n, nv, lagged ? W.Vc(r, j) : nullptr, W.vec(W.w, r), n, W.partr(r), W.redr(r),
-                         s, gl));
+        DW_TRY(gs_reduce(W.vprec, V, n, nv, lagged ? W.Vc(r, j) : nullptr, W.wr(r), n, W.partr(r), W.redr(r), s,
+                         gl, nullptr, wprec));
         DW_TRY(dense_gs_coef(W.Hr(r), nv, lagged ? j : -1, j, lagged ? 1 : 0, 1, W.redr(r), W.coefr(r), W.scalr(r),
                              kBdTol, s, gl));
-        DW_TRY(gs_update(W.vprec, V, n, nv, lagged ? j : -1, W.vec(W.w, r), W.Vc(r, j + 1), W.coefr(r), n,
-                         W.partr(r), W.nrmr(r), s, gl));
+        DW_TRY(gs_update(W.vprec, V, n, nv, lagged ? j : -1, W.wr(r), W.Vc(r, j + 1), W.coefr(r), n, W.partr(r),
+                         W.nrmr(r), s, gl, nullptr, wprec));
         DW_TRY(dense_step2(W.Hr(r), j, W.nrmr(r), W.cr(r), W.scalr(r), kBdTol, s, W.ctlr(r), W.ctldr(r)));
       }
     }
@@ -317,13 +357,17 @@ struct Solver {
       const int* gfin = W.gate(r, kCFin);
       const int* gcyc = W.gate(r, kCInCycle);
       void* V = W.Vr(r);
-      DW_TRY(gs_reduce(W.vprec, V, n, m, nullptr, nullptr, n, W.partr(r), W.redr(r), s, gfin, jend));
+      ProfTag tag_fin(kTagFin, 1ull << r);
+      DW_TRY(gs_reduce(W.vprec, V, n, m, nullptr, nullptr, n, W.partr(r), W.redr(r), s, gfin, jend, wprec));
       DW_TRY(dense_gs_coef(W.Hr(r), m, m, -1, 1, 0, W.redr(r), W.coefr(r), W.scalr(r), kBdTol, s, gfin, jend));
-      DW_TRY(gs_update(W.vprec, V, n, m, m, nullptr, nullptr, W.coefr(r), n, W.partr(r), nullptr, s, gfin, jend));
+      DW_TRY(gs_update(W.vprec, V, n, m, m, nullptr, nullptr, W.coefr(r), n, W.partr(r), nullptr, s, gfin, jend,
+                       wprec));
+      ProfTag tag_cyc(kTagCycle, 1ull << r);
       DW_TRY(dense_lsq(W.Hr(r), m, W.cr(r), W.etar(r), W.scalr(r), s, gcyc, jend));
-      DW_TRY(blas_combine(DW_PREC_F64, W.Zr(r), n, m, W.etar(r), 1.0, W.vec(W.x, r), n, s, gcyc, jend));
+      DW_TRY(blas_combine(W.zstore, W.Zr(r), n, m, W.etar(r), 1.0, W.vec(W.x, r), n, s, gcyc, jend));
     }
     const int* rl_end = sh.rl.as<int>() + (size_t)m * nr;
+    ProfTag tag_end(kTagCycle, rhs_mask(present));
     DW_TRY(launch_dslash_outer(g, 0.0, DW_PREC_F64, W.x.p, 1.0, f->U[DW_PREC_F64], W.r.as<double>(),
                                W.b.as<double>(), 1, (int)present.size(), n, n, s, rl_end, f->C[DW_PREC_F64],
                                gate_cyc, kCtl, mass));
@@ -339,6 +383,7 @@ struct Solver {
     if (sh.donor) {
       for (int r : present) {
         if (r == 0) continue;
+        ProfTag tag_p(kTagCycle, 1ull << r);
         projected |= 1ull << r;
         const int* gcyc = W.gate(r, kCInCycle);
         double* pr = W.projr(r);
@@ -347,13 +392,15 @@ struct Solver {
         double* sv = y + 2 * kMaxM;
         DW_TRY(blas_dots(W.vprec, W.Vr(0), n, k + 1, W.vec(W.r, r), n, W.partr(r), t, 1, 0, s, gcyc));
         DW_TRY(dense_project(W.Hr(0), k, t, y, sv, s, gcyc));
-        DW_TRY(blas_combine(DW_PREC_F64, W.Zr(0), n, k, y, 1.0, W.vec(W.x, r), n, s, gcyc));
+        DW_TRY(blas_combine(W.zstore, W.Zr(0), n, k, y, 1.0, W.vec(W.x, r), n, s, gcyc));
         DW_TRY(blas_combine(W.vprec, W.Vr(0), n, k + 1, sv, -1.0, W.vec(W.r, r), n, s, gcyc));
       }
     }
-    for (int r : present)
+    for (int r : present) {
+      ProfTag tag_n(kTagCycle, 1ull << r);
       DW_TRY(blas_dots(DW_PREC_F64, W.vec(W.r, r), n, 1, W.vec(W.r, r), n, W.partr(r), W.nrmr(r), 1, 0, s,
                        W.gate(r, kCInCycle)));
+    }
     DW_TRY(ctl_decide(W.ctl.as<int>(), W.ctld.as<double>(), W.nrm.as<double>(), 2, W.scal.as<double>(), kSclCount,
                       nr, k, projected, s));
 
@@ -362,6 +409,7 @@ struct Solver {
       for (int r : present) {
         const int* gd = W.gate(r, kCDefl);
         const int* jend = W.gate(r, kCJend);
+        ProfTag tag_d(kTagDefl, 1ull << r);
         if (inject) {
           // G_{k+1}'s last column from the explicit residual: V_{m+1}^H r with
           // eta = 0 (the kernel forms c - H^ eta)
@@ -379,13 +427,15 @@ struct Solver {
       for (int r : present) {
         const int* gd = W.gate(r, kCDefl);
         const int* jend = W.gate(r, kCJend);
+        ProfTag tag_d(kTagDefl, 1ull << r);
         DW_TRY(blas_rotate(W.vprec, W.Vr(r), n, m + 1, W.Qr(r), kLd, k + 1, n, s, gd, jend, 1));
-        DW_TRY(blas_rotate(DW_PREC_F64, W.Zr(r), n, m, W.Qr(r), kLd, k, n, s, gd, jend, 0));
+        DW_TRY(blas_rotate(W.zstore, W.Zr(r), n, m, W.Qr(r), kLd, k, n, s, gd, jend, 0));
       }
       if (inject)
         for (int r : present) DW_TRY(inject_vector(r));
       for (int r : present) {
         const int* gd = W.gate(r, kCDefl);
+        ProfTag tag_d(kTagDefl, 1ull << r);
         DW_TRY(fill_zero(W.cr(r), 2 * (long long)kLd, gd, s));
         DW_TRY(blas_dots(W.vprec, W.Vr(r), n, k + 1, W.vec(W.r, r), n, W.partr(r), W.cr(r), 1, 0, s, gd));
       }
@@ -404,6 +454,7 @@ struct Solver {
     const long long n = W.n;
     const int k = W.k;
     const int* gd = W.gate(r, kCDefl);
+    ProfTag tag_d(kTagDefl, 1ull << r);
     double* w = W.vec(W.w, r);
     double* t = W.injr(r) + 2 * kLd;
     double* tail = W.injr(r) + 4 * kLd;
@@ -417,6 +468,7 @@ struct Solver {
     DW_TRY(blas_dots(DW_PREC_F64, w, n, 1, w, n, W.partr(r), tail + 2, 1, 0, s, gd));
     DW_TRY(inject_coef(W.ctlr(r), W.ctldr(r), tail, coef, s));
     const int* gi = W.gate(r, kCInject);
+    ProfTag tag_i(kTagInject, 1ull << r);
     if (W.vprec == DW_PREC_F64) {
       DW_TRY(fill_zero((double*)W.Vc(r, k), 2 * n, gi, s));
       DW_TRY(blas_combine(DW_PREC_F64, w, n, 1, coef, 1.0, (double*)W.Vc(r, k), n, s, gi));
@@ -474,6 +526,20 @@ struct Solver {
       }
       DW_TRY(run_cycle(*sh, graphs));
       DW_TRY(readback(W, s));
+      // per-kernel timing: a launch counts for the right-hand sides whose gate was open
+      prof_resolve([&](int kind, int r) {
+        if (r >= nr) return false;
+        const int* c = W.hctl(r);
+        if (kind >= 0) return c[kCPrevInCycle] && kind >= c[kCPrevJ0] && kind < c[kCPrevJend];
+        switch (kind) {
+          case kTagFin: return c[kCPrevFin] != 0;
+          case kTagCycle: return c[kCPrevInCycle] != 0;
+          case kTagDefl: return c[kCPrevDefl] != 0;
+          case kTagFresh: return c[kCPrevFresh] != 0;
+          case kTagInject: return c[kCPrevInject] != 0;
+          default: return true;
+        }
+      });
       bool any = false;
       for (int r = 0; r < nr; ++r) {
         const int* c = W.hctl(r);
@@ -528,8 +594,9 @@ void destroy_cache(void* p) { delete static_cast<SolverCache*>(p); }
 
 namespace dw {
 size_t solver_bytes(long long sites, int m, int prec, int flags, int nrhs) {
-  const int vprec = (flags & DW_SOLVE_V32) ? DW_PREC_F32 : DW_PREC_F64;
-  return bytes_per_rhs(sites * 12, m, prec, vprec) * (size_t)nrhs + (size_t)nrhs * 64 * 1024;
+  const int vprec = (flags & (DW_SOLVE_V32 | DW_SOLVE_A32)) ? DW_PREC_F32 : DW_PREC_F64;
+  const int zstore = (flags & DW_SOLVE_A32) ? DW_PREC_F32 : DW_PREC_F64;
+  return bytes_per_rhs(sites * 12, m, prec, vprec, zstore) * (size_t)nrhs + (size_t)nrhs * 64 * 1024;
 }
 }  // namespace dw
 
@@ -548,7 +615,7 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
     return DW_EINVAL;
   }
   DW_TRY(check_sap_params(f->g, &P->sap));
-  if (P->flags & ~(DW_SOLVE_GRAPHS | DW_SOLVE_V32 | DW_SOLVE_INJECT)) {
+  if (P->flags & ~(DW_SOLVE_GRAPHS | DW_SOLVE_V32 | DW_SOLVE_INJECT | DW_SOLVE_A32)) {
     set_error("fgmresdr_solve: unknown flags 0x%x", (unsigned)P->flags);
     return DW_EINVAL;
   }
@@ -569,17 +636,17 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
   // captured cycles need a stream that can be captured and no per-launch event timing
   const bool graphs = (P->flags & DW_SOLVE_GRAPHS) && stream != nullptr && !f->ctx->prof.on;
   SolverCache* cache = static_cast<SolverCache*>(f->solver_cache);
-  // RHS per batch: as many as fit in free device memory (at least one); the
-  // shared deflation space's projection mask covers 64 right-hand sides
+  // RHS per batch: as many as fit in free device memory (at least one), at
+  // most kMaxBatch (the per-RHS masks of a batch are 64 bits wide)
   size_t free_b = 0, total_b = 0;
   DW_CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t per = bytes_per_rhs(n, P->m, P->sap.storage, basis_prec(P));
+  const size_t per = bytes_per_rhs(n, P->m, P->sap.storage, basis_prec(P), zstore_prec(P));
   const bool reuse = graphs && cache && cache->W && cache->W->nr == nrhs && same_params(cache->W->P, *P) &&
                      cache->W->clover[0] == f->C[P->sap.storage] && cache->W->clover[1] == f->C[DW_PREC_F64];
   int nb = (int)std::max<size_t>(1, (size_t)(0.9 * (double)free_b) / per);
   if (reuse) nb = nrhs;
   nb = std::min(nb, (int)nrhs);
-  if (P->shared_defl) nb = std::min(nb, 64);
+  nb = std::min(nb, kMaxBatch);
   if (graphs && !reuse && cache) {
     // parameters changed: the old workspace goes before the new one is made
     DW_CHECK_HIP(hipStreamSynchronize(stream));

@@ -68,13 +68,15 @@ def test_sap_full_size_sampled_blocks(big, prec, tol):
     assert e0 < tol, e0
 
 
-@pytest.mark.parametrize("flags", [0, P.SOLVE_V32])
+@pytest.mark.parametrize("flags", [0, P.SOLVE_V32, P.SOLVE_A32 | P.SOLVE_INJECT])
 def test_solve_full_size_true_residual(big, flags):
     U, f, m0 = big
     b = synth.gaussian_spinor(L, 1000)
     prm = P.SolverParams(m=30, k=12, max_iter=2000, tol=1e-10, flags=flags,
                          sap=P.SapParams(block=B, ncycles=13, nmr=8, storage=P.DW_PREC_F16))
     x, st = f.solve(m0, prm, P.to_device(b))
+    print(f"32^3x64 solve flags {flags}: {st[0].iterations} it, {st[0].cycles} cycles, "
+          f"{st[0].clean_restarts} clean restarts", flush=True)
     assert st[0].converged and st[0].true_relres <= 1e-10
     x = x.cpu().numpy()
     r = b - W.apply_D(U, m0, x)

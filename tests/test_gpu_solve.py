@@ -200,7 +200,7 @@ def test_graph_captured_steps_equal_eager(c1):
     prm.flags = 0
     x1, _ = f.solve(M01, prm, P.to_device(b))
     assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
-    prm.flags = 8
+    prm.flags = 16
     with pytest.raises(P.DwError):
         f.solve(M01, prm, P.to_device(b))
 
