@@ -34,7 +34,6 @@ struct Geom {
   int nbc;         // blocks per colour (nblk / 2)
   int lstride[4];  // local index stride per direction: 1, Bx, Bx*By, Bx*By*Bz
   long long V;     // sites
-  int T[4];        // launch tile of the whole-lattice operator, in blocks (see tiled_block)
 };
 
 // Validates and fills a Geom. Returns 0 on success, else a static message.
@@ -62,26 +61,7 @@ inline const char* make_geom(const int L[4], const int B[4], Geom* g) {
   g->lstride[1] = B[0];
   g->lstride[2] = B[0] * B[1];
   g->lstride[3] = B[0] * B[1] * B[2];
-  for (int mu = 0; mu < 4; ++mu) g->T[mu] = 1;
   return nullptr;
-}
-
-// Block of the i-th workgroup of the whole-lattice operator: blocks are
-// visited tile by tile (tiles of T blocks, lexicographic), lexicographic
-// within a tile, so that the workgroups running together on one XCD read
-// each other's faces through its L2. T = 1 is the plain lexicographic order.
-__host__ __device__ __forceinline__ int tiled_block(const Geom& g, int i) {
-  const int tv = g.T[0] * g.T[1] * g.T[2] * g.T[3];
-  int w = i % tv, q = i / tv;
-  int bc[4];
-  for (int mu = 0; mu < 4; ++mu) {
-    const int nt = g.N[mu] / g.T[mu];
-    const int wm = w % g.T[mu], qm = q % nt;
-    w /= g.T[mu];
-    q /= nt;
-    bc[mu] = qm * g.T[mu] + wm;
-  }
-  return bc[0] + g.N[0] * (bc[1] + g.N[1] * (bc[2] + g.N[2] * bc[3]));
 }
 
 __host__ __device__ __forceinline__ void decode_block(const Geom& g, int b, int bc[4]) {

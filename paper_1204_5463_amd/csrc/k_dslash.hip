@@ -115,9 +115,8 @@ __global__ void __launch_bounds__(MAXT)
   // same links run together on one XCD
   const int wi = xcd_remap(blockIdx.x, g.nblk * nr);
   if (wi < 0) return;  // uniform for the workgroup
-  const int bi = wi / nr;
-  const int b = tiled_block(g, bi);
-  const int rhs = rlist ? rlist[wi - bi * nr] : wi - bi * nr;
+  const int b = wi / nr;
+  const int rhs = rlist ? rlist[wi - b * nr] : wi - b * nr;
   if (dc.gate && dc.gate[(long long)rhs * dc.gstride] == 0) return;  // uniform for the workgroup
   if (dc.dmass) diag = (T)(4.0 + *dc.dmass);
   const int l = threadIdx.x;

@@ -8,7 +8,9 @@ D(m0) = D(0) + m0 I exactly, the eigenvalue of D(m0) closest to the left
 edge is lambda_edge + m0; the critical mass is m_c = -Re(lambda_edge) and
 a near-critical mass is m0 = m_c + delta.
 
-Usage: python tests/golden/tune_critical_mass.py [name ...]
+Usage: python tests/golden/tune_critical_mass.py [--quick] [name ...]
+  --quick: 4 Ritz values, ncv 24, tol 1e-7 (enough for the critical mass
+           to about 1e-5; for lattices where the default settings take hours)
 """
 import fcntl
 import json
@@ -68,12 +70,17 @@ def leftmost(L, eps, seed, csw=0.0, nev=12, ncv=64, tol=1e-9):
     return ev, count[0], time.time() - t0
 
 
-def main(names):
+QUICK = dict(nev=4, ncv=24, tol=1e-7)
+
+
+def main(names, quick=False):
     for name in names:
         L, eps, seed = FIELDS[name][:3]
         csw = FIELDS[name][3] if len(FIELDS[name]) > 3 else 0.0
         opts = dict(nev=12, ncv=64, tol=1e-9)
         opts.update(FIELDS[name][4] if len(FIELDS[name]) > 4 else {})
+        if quick:
+            opts.update(QUICK)
         ev, nmv, secs = leftmost(L, eps, seed, csw, **opts)
         # several runs may finish at once: read-modify-write under a lock
         lock = open(OUT + ".lock", "w")
@@ -96,4 +103,5 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(FIELDS))
+    args = [a for a in sys.argv[1:] if a != "--quick"]
+    main(args or list(FIELDS), quick="--quick" in sys.argv[1:])
