@@ -485,6 +485,53 @@ __device__ __forceinline__ void hop_sum_block_ahead(int l, XB&& xin_blk, UB&& u_
   }
 }
 
+// The same in-block hop sum with the direction loop unrolled at compile
+// time: every hop is a straight-line body under its lane mask (no switch
+// over the hop index), so the accumulator stays in the same registers
+// across hops instead of being copied through the merge points.
+template <int MU, int BS, typename T, typename SG, typename XB, typename UB, typename W>
+__device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk, cplx<T> acc[12], W wf[9]) {
+  constexpr int LB = ilog2(BS);
+  constexpr int st = 1 << (LB * MU);
+  const int lcm = (l >> (LB * MU)) & (BS - 1);
+  const int ub = lcm > 0 ? l - st : l;
+  W wb[9];
+  // keep each direction's loads inside its own stretch of code (hoisted,
+  // the next directions' links would not fit the register budget)
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) wb[e] = u_blk(MU, e, ub);
+  auto do_hop = [&](auto dirc, auto&& psi, auto&& u) {
+    constexpr int DIR = decltype(dirc)::value;
+    if constexpr (std::is_same<SG, h2v>::value) hop16p<MU, DIR>(acc, psi, u);
+    else if constexpr (is_link16<SG>) hop16<MU, DIR, SG>(acc, psi, u);
+    else hop<MU, DIR, T>(acc, psi, u);
+  };
+  if (lcm < BS - 1)
+    do_hop(std::integral_constant<int, 1>{}, [&](int k) { return xin_blk(l + st, k); }, [&](int e) { return wf[e]; });
+  if constexpr (MU < 3) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) wf[e] = u_blk(MU + 1, e, l);
+  }
+  if (lcm > 0)
+    do_hop(std::integral_constant<int, -1>{}, [&](int k) { return xin_blk(l - st, k); }, [&](int e) { return wb[e]; });
+}
+
+template <typename T, typename SG, int BS, typename XB, typename UB>
+__device__ __forceinline__ void hop_sum_block_unrolled(int l, XB&& xin_blk, UB&& u_blk, cplx<T> acc[12]) {
+  static_assert(BS > 0 && (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
+  using W = decltype(u_blk(0, 0, 0));
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
+  W wf[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) wf[e] = u_blk(0, e, l);
+  block_dir_unrolled<0, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
+  block_dir_unrolled<1, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
+  block_dir_unrolled<2, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
+  block_dir_unrolled<3, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
+}
+
 // Full hopping sum (faces included) for compile-time BS^4 blocks: each hop's
 // neighbour spinor is read into registers first, from the block (xin_blk,
 // in-block sites) or from the neighbouring block (xin_halo, face sites), so
