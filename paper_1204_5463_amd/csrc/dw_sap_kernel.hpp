@@ -28,6 +28,8 @@
 // by a fixed-order sum over the workgroup's waves (deterministic).
 #pragma once
 
+#include <cfloat>
+
 #include <type_traits>
 
 #include "dw_clover.hpp"
@@ -273,9 +275,18 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
       nim += rb[w * 3 + 1];
       den += rb[w * 3 + 2];
     }
-    const cplx<T> alpha = den > (T)0 ? mk<T>(nre / den, nim / den) : mk<T>(0, 0);
+    // alpha = (p2^H rho) / (p2^H p2); in FP32 one hardware reciprocal
+    // (1 ulp) replaces the two IEEE divisions
+    cplx<T> alpha = mk<T>(0, 0);
+    if constexpr (std::is_same<T, float>::value) {
+      const float inv = den > FLT_MIN ? __builtin_amdgcn_rcpf(den) : 0.f;
+      alpha = mk<T>(nre * inv, nim * inv);
+      if (adapt) rr -= (nre * nre + nim * nim) * inv;
+    } else if (den > (T)0) {
+      alpha = mk<T>(nre / den, nim / den);
+      if (adapt) rr -= (nre * nre + nim * nim) / den;
+    }
     const cplx<T> alpha_y = mk<T>(alpha.re + alpha.re, alpha.im + alpha.im);
-    if (adapt && den > (T)0) rr -= (nre * nre + nim * nim) / den;
     if (active) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) {

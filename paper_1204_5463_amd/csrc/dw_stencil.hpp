@@ -447,48 +447,7 @@ __device__ __forceinline__ void hop_sum_staged(const Geom& g, int b, int l, cons
   }
 }
 
-// In-block hopping sum of D^l (eq. 2) for compile-time BS^4 blocks, with
-// the link loads one hop ahead: per direction the backward hop's links are
-// loaded before the forward hop's arithmetic and the next direction's
-// forward links before the backward hop's, so each hop's L1/L2 latency
-// overlaps the previous hop's work. Sites on the lower face load their own
-// link in place of the (skipped) backward one, which keeps every load inside
-// the block. u_blk(mu, e, local site) returns a link entry as the hop takes it.
-template <typename T, typename SG, int BS, typename XB, typename UB>
-__device__ __forceinline__ void hop_sum_block_ahead(int l, XB&& xin_blk, UB&& u_blk, cplx<T> acc[12]) {
-  static_assert(BS > 0 && (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
-  constexpr int LB = ilog2(BS);
-  using W = decltype(u_blk(0, 0, 0));
-  auto dispatch = [&](int h, auto&& psi, auto&& u) {
-    if constexpr (std::is_same<SG, h2v>::value) hop16p_dispatch(h, acc, psi, u);
-    else if constexpr (is_link16<SG>) hop16_dispatch<SG>(h, acc, psi, u);
-    else hop_dispatch<T>(h, acc, psi, u);
-  };
-#pragma unroll
-  for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
-  W wf[9], wb[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) wf[e] = u_blk(0, e, l);
-#pragma unroll 1
-  for (int mu = 0; mu < 4; ++mu) {
-    const int st = 1 << (LB * mu);
-    const int lcm = (l >> (LB * mu)) & (BS - 1);
-    const int ub = lcm > 0 ? l - st : l;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) wb[e] = u_blk(mu, e, ub);
-    if (lcm < BS - 1) dispatch(2 * mu, [&](int k) { return xin_blk(l + st, k); }, [&](int e) { return wf[e]; });
-    if (mu < 3) {
-#pragma unroll
-      for (int e = 0; e < 9; ++e) wf[e] = u_blk(mu + 1, e, l);
-    }
-    if (lcm > 0) dispatch(2 * mu + 1, [&](int k) { return xin_blk(l - st, k); }, [&](int e) { return wb[e]; });
-  }
-}
-
-// The same in-block hop sum with the direction loop unrolled at compile
-// time: every hop is a straight-line body under its lane mask (no switch
-// over the hop index), so the accumulator stays in the same registers
-// across hops instead of being copied through the merge points.
+// One direction of hop_sum_block_unrolled (below).
 template <int MU, int BS, typename T, typename SG, typename XB, typename UB, typename W>
 __device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk, cplx<T> acc[12], W wf[9]) {
   constexpr int LB = ilog2(BS);
@@ -517,6 +476,16 @@ __device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk
     do_hop(std::integral_constant<int, -1>{}, [&](int k) { return xin_blk(l - st, k); }, [&](int e) { return wb[e]; });
 }
 
+// In-block hopping sum of D^l (eq. 2) for compile-time BS^4 blocks, with
+// the link loads one hop ahead: per direction the backward hop's links are
+// loaded before the forward hop's arithmetic and the next direction's
+// forward links before the backward hop's, so each hop's L1/L2 latency
+// overlaps the previous hop's work. Sites on the lower face load their own
+// link in place of the (skipped) backward one, which keeps every load inside
+// the block. u_blk(mu, e, local site) returns a link entry as the hop takes it.
+// Directions are unrolled at compile time: every hop is a straight-line
+// body under its lane mask (no switch over the hop index), so the
+// accumulator stays in the same registers from hop to hop.
 template <typename T, typename SG, int BS, typename XB, typename UB>
 __device__ __forceinline__ void hop_sum_block_unrolled(int l, XB&& xin_blk, UB&& u_blk, cplx<T> acc[12]) {
   static_assert(BS > 0 && (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
@@ -539,7 +508,7 @@ __device__ __forceinline__ void hop_sum_block_unrolled(int l, XB&& xin_blk, UB&&
 // source around the whole hop would run it twice on the faces of x, y, z).
 // Links: u_at(block, mu, e, local site); the backward hop's link comes from
 // this block or from the neighbouring block per lane, loaded one hop ahead
-// as in hop_sum_block_ahead.
+// as in hop_sum_block_unrolled.
 template <typename T, typename SG, int BS, typename XB, typename XH, typename UA>
 __device__ __forceinline__ void hop_sum_halo_ahead(const Geom& g, int b, int l, const int bc[4], XB&& xin_blk,
                                                    XH&& xin_halo, UA&& u_at, cplx<T> acc[12]) {
