@@ -255,17 +255,6 @@ def serve(args):
     for n in names:
         src = next(s for s in SERVE_MASS[n] if s in crit)
         mc[n] = (crit[src]["m_c"], src)
-    reqs, t = [], 0.0
-    for i in range(args.requests):
-        t += rng.exponential(args.mean_gap)
-        n = names[int(rng.integers(len(names)))]
-        nrhs = int(rng.integers(1, args.max_rhs + 1))
-        delta = float(np.exp(rng.uniform(np.log(2e-3), np.log(2e-2))))
-        reqs.append(dict(arrival=t, lattice=n, nrhs=nrhs, m0=mc[n][0] + delta, seed=3000 + 100 * i))
-    for r in reqs:
-        r["b"] = P.to_device(synth.gaussian_spinors(SERVE_LATTICES[r["lattice"]], r["nrhs"], seed0=r["seed"]))
-    log(f"[serve] {len(reqs)} requests over {t:.2f} s of arrivals")
-
     # SAP parameters from the time-to-solution tuning at 32^3x64 (the flat
     # optimum s = 6..8, nMR = 7..10), the same for every request
     def params(storage, graphs=False):
@@ -273,6 +262,40 @@ def serve(args):
                               flags=P.SOLVE_GRAPHS if graphs else 0,
                               sap=P.SapParams(block=(4, 4, 4, 4), ncycles=args.serve_cycles, nmr=8,
                                               storage=storage))
+
+    # RHS per request: 1..max_rhs, capped per lattice so that two requests
+    # of the largest count fit the server's budget (0.8 of free memory)
+    # side by side, by the footprint the server itself charges
+    free = torch.cuda.mem_get_info()[0]
+    cap = {}
+    for n in names:
+        L = SERVE_LATTICES[n]
+        bmax = torch.empty((args.max_rhs,) + synth.lattice_shape(L) + (4, 3), dtype=torch.complex128, device="cuda")
+        c = 1
+        for k in range(1, args.max_rhs + 1):
+            fp = P.Server.footprint(L, (4, 4, 4, 4), mc[n][0], fields[n], bmax[:k], params(P.DW_PREC_F16))
+            if 2 * fp <= 0.8 * free:
+                c = k
+        cap[n] = c
+        del bmax
+    torch.cuda.empty_cache()
+    log(f"[serve] RHS caps per lattice: {cap}")
+    reqs, t = [], 0.0
+    for i in range(args.requests):
+        t += rng.exponential(args.mean_gap)
+        n = names[int(rng.integers(len(names)))]
+        nrhs = min(int(rng.integers(1, args.max_rhs + 1)), cap[n])
+        delta = float(np.exp(rng.uniform(np.log(2e-3), np.log(2e-2))))
+        reqs.append(dict(arrival=t, lattice=n, nrhs=nrhs, m0=mc[n][0] + delta, seed=3000 + 100 * i))
+    log(f"[serve] {len(reqs)} requests over {t:.2f} s of arrivals, {sum(r['nrhs'] for r in reqs)} RHS")
+
+    def rhs_of(r):
+        # the request's right-hand sides, made on the device when it is sent
+        # (seeded Gaussian entries; the serial baseline draws the same)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(r["seed"])
+        shp = (r["nrhs"],) + synth.lattice_shape(SERVE_LATTICES[r["lattice"]]) + (4, 3)
+        return torch.randn(shp, dtype=torch.complex128, device="cuda", generator=gen)
 
     ctx = P.Context(0)
     # warm the kernels of every lattice once (untimed)
@@ -285,75 +308,91 @@ def serve(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    srv = P.Server(ctx, slots=args.slots, queue_capacity=len(reqs))
-    pending, done = {}, {}
-    t0 = time.perf_counter()
-    i = 0
-    while i < len(reqs) or pending:
-        now = time.perf_counter() - t0
-        while i < len(reqs) and reqs[i]["arrival"] <= now:
-            r = reqs[i]
-            tk = srv.submit(SERVE_LATTICES[r["lattice"]], (4, 4, 4, 4), r["m0"], fields[r["lattice"]], r["b"],
-                            params(P.DW_PREC_F16, graphs=args.serve_graphs))
-            pending[tk] = i
-            i += 1
-        for tk in list(pending):
-            out = srv.poll(tk)
-            if out is not None:
-                x, st, tm = out
-                k = pending.pop(tk)
-                done[k] = (st, tm, time.perf_counter() - t0)
-                r = reqs[k]
-                log(f"[serve] request {k} {r['lattice']} nrhs={r['nrhs']} done: "
-                    f"{max(s.iterations for s in st)} it, latency {tm['latency']:.3f} s")
-                del x
-        time.sleep(2e-4)
-    makespan = time.perf_counter() - t0
-    srv.close()
-    lat = [done[k][1]["latency"] for k in range(len(reqs))]
-    conv = all(s.converged for k in range(len(reqs)) for s in done[k][0])
-    rhs_total = sum(r["nrhs"] for r in reqs)
-
-    # serial all-FP64 baseline: same order, one request at a time
-    log("[serve] serial FP64 baseline")
-    svc = []
-    for k, r in enumerate(reqs):
-        L = SERVE_LATTICES[r["lattice"]]
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        f = P.Field(ctx, L, (4, 4, 4, 4), fields[r["lattice"]])
-        _, st = f.solve(r["m0"], params(P.DW_PREC_F64, graphs=False), r["b"], raise_on_notconv=False)
-        f.close()
-        torch.cuda.synchronize()
-        svc.append(time.perf_counter() - ts)
-        log(f"[serve] serial {k}: {svc[-1]:.3f} s")
-    fin, lat64 = 0.0, []
-    for r, sv in zip(reqs, svc):
-        fin = max(fin, r["arrival"]) + sv
-        lat64.append(fin - r["arrival"])
     line = {
         "metric": "serving throughput (requests/s) of a Poisson stream of solve requests, continuous batching",
-        "value": round(len(reqs) / makespan, 4),
+        "value": None,
         "unit": "requests/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, exponential gaps mean {args.mean_gap * 1e3:.0f} ms (seed 20), "
-                               f"lattices {names} uniform, nrhs 1..{args.max_rhs}, eps=0.6 links, "
-                               f"m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s={args.serve_cycles} nMR=8, FGMRES-DR(30,12), tol 1e-10, "
-                               f"{args.slots} slots" + (", captured steps" if args.serve_graphs else ""),
+                               f"lattices {names} uniform, nrhs 1..{args.max_rhs} capped per lattice {cap}, "
+                               f"eps=0.6 links, m0 = m_c + logU[2e-3, 2e-2], FP16 SAP 4^4 s={args.serve_cycles} nMR=8, "
+                               f"FGMRES-DR(30,12), tol 1e-10, {args.slots} slots, restart cycles replayed as HIP graphs",
                    "m_c_from": {n: mc[n][1] for n in names}},
-        "makespan_s": round(makespan, 3),
+        "requests": len(reqs),
+        "rhs_total": sum(r["nrhs"] for r in reqs),
         "offered_requests_per_s": round(len(reqs) / reqs[-1]["arrival"], 4),
-        "rhs_solves_per_s": round(rhs_total / makespan, 4),
-        "p50_latency_ms": round(1e3 * pct(lat, 0.5), 1),
-        "p99_latency_ms": round(1e3 * pct(lat, 0.99), 1),
-        "all_converged": conv,
-        "serial_fp64": {"requests_per_s": round(len(reqs) / fin, 4) if fin > 0 else None,
-                        "busy_s": round(sum(svc), 3),
-                        "p50_latency_ms": round(1e3 * pct(lat64, 0.5), 1),
-                        "p99_latency_ms": round(1e3 * pct(lat64, 0.99), 1)},
     }
+    rhs_total = line["rhs_total"]
+    if args.serve_part in ("both", "mixed"):
+        # Requests wait on the host until the server holds fewer than
+        # slots + 2 unfinished ones (their inputs and outputs then go to
+        # device memory), as a client would queue them; latency runs from
+        # the arrival time.
+        srv = P.Server(ctx, slots=args.slots, queue_capacity=args.slots + 2)
+        pending, done, lat = {}, {}, [0.0] * len(reqs)
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i]["arrival"] <= now and len(pending) < args.slots + 2:
+                r = reqs[i]
+                tk = srv.submit(SERVE_LATTICES[r["lattice"]], (4, 4, 4, 4), r["m0"], fields[r["lattice"]], rhs_of(r),
+                                params(P.DW_PREC_F16, graphs=True))
+                pending[tk] = i
+                i += 1
+            for tk in list(pending):
+                out = srv.poll(tk)
+                if out is not None:
+                    x, st, tm = out
+                    k = pending.pop(tk)
+                    fin = time.perf_counter() - t0
+                    done[k] = (st, tm, fin)
+                    lat[k] = fin - reqs[k]["arrival"]
+                    r = reqs[k]
+                    log(f"[serve] request {k} {r['lattice']} nrhs={r['nrhs']} done: "
+                        f"{max(s.iterations for s in st)} it, latency {lat[k]:.3f} s")
+                    del x
+            time.sleep(2e-4)
+        makespan = time.perf_counter() - t0
+        srv.close()
+        line.update({
+            "value": round(len(reqs) / makespan, 4),
+            "makespan_s": round(makespan, 3),
+            "rhs_solves_per_s": round(rhs_total / makespan, 4),
+            "p50_latency_ms": round(1e3 * pct(lat, 0.5), 1),
+            "p99_latency_ms": round(1e3 * pct(lat, 0.99), 1),
+            "all_converged": all(s.converged for k in range(len(reqs)) for s in done[k][0]),
+        })
+
+    if args.serve_part in ("both", "fp64"):
+        # serial all-FP64 baseline: same order, one request at a time
+        log("[serve] serial FP64 baseline")
+        svc = []
+        conv64 = True
+        for k, r in enumerate(reqs):
+            L = SERVE_LATTICES[r["lattice"]]
+            b = rhs_of(r)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            f = P.Field(ctx, L, (4, 4, 4, 4), fields[r["lattice"]])
+            _, st = f.solve(r["m0"], params(P.DW_PREC_F64, graphs=False), b, raise_on_notconv=False)
+            f.close()
+            torch.cuda.synchronize()
+            svc.append(time.perf_counter() - ts)
+            conv64 = conv64 and all(x.converged for x in st)
+            log(f"[serve] serial {k} {r['lattice']} nrhs={r['nrhs']}: {svc[-1]:.3f} s")
+        fin, lat64 = 0.0, []
+        for r, sv in zip(reqs, svc):
+            fin = max(fin, r["arrival"]) + sv
+            lat64.append(fin - r["arrival"])
+        line["serial_fp64"] = {"requests_per_s": round(len(reqs) / fin, 4) if fin > 0 else None,
+                               "rhs_solves_per_s": round(rhs_total / fin, 4) if fin > 0 else None,
+                               "busy_s": round(sum(svc), 3),
+                               "p50_latency_ms": round(1e3 * pct(lat64, 0.5), 1),
+                               "p99_latency_ms": round(1e3 * pct(lat64, 0.99), 1),
+                               "all_converged": conv64}
     print(json.dumps(line), flush=True)
 
 
@@ -443,13 +482,13 @@ def main():
     ap.add_argument("--autotune", default=None, metavar="CACHE.json",
                     help="tune (block, nMR, s, m, k) by time to solution before timing (cached in this file)")
     ap.add_argument("--serve", action="store_true", help="run the serving stream instead of the solve benchmark")
-    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
-    ap.add_argument("--max-rhs", type=int, default=4)
+    ap.add_argument("--max-rhs", type=int, default=12)
     ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--serve-cycles", type=int, default=6, help="serving: SAP cycles per application")
-    ap.add_argument("--serve-graphs", action="store_true",
-                    help="serving: replay captured Arnoldi steps (HIP graphs) in single-RHS requests")
+    ap.add_argument("--serve-part", choices=("both", "mixed", "fp64"), default="both",
+                    help="serving: run the server stream, the serial all-FP64 baseline, or both")
     ap.add_argument("--sap-study", action="store_true",
                     help="SAP as a stand-alone solver at masses around the critical one, fixed and adaptive "
                          "MR block solves, instead of the solve benchmark")

@@ -274,8 +274,10 @@ __device__ __forceinline__ h2v cj16(h2v v) { return h2v{v.x, -v.y}; }
 __device__ __forceinline__ h2v sw16(h2v v) { return h2v{v.y, v.x}; }
 __device__ __forceinline__ h2v swn16(h2v v) { return h2v{v.y, -v.x}; }
 
+// g = W h for the half spinor h of hop (MU, DIR), packed FP16 operands:
+// the projection and the two SU(3) products of hop16p without the rebuild.
 template <int MU, int DIR, typename PsiF, typename UF>
-__device__ __forceinline__ void hop16p(cplx<float> acc[12], PsiF&& psi, UF&& u) {
+__device__ __forceinline__ void hop16p_g(PsiF&& psi, UF&& u, cplx<float> g0[3], cplx<float> g1[3]) {
   using P = proj_table<MU>;
   constexpr int A = DIR > 0 ? P::a : neg(P::a);
   constexpr int B = DIR > 0 ? P::b : neg(P::b);
@@ -296,7 +298,6 @@ __device__ __forceinline__ void hop16p(cplx<float> acc[12], PsiF&& psi, UF&& u) 
       b1[b] = swn16(p1) + swn16(q1);
     }
   }
-  cplx<float> g0[3], g1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const h2v w0 = u(DIR > 0 ? a * 3 : a);
@@ -313,6 +314,12 @@ __device__ __forceinline__ void hop16p(cplx<float> acc[12], PsiF&& psi, UF&& u) 
     g0[a] = mk(r0, i0);
     g1[a] = mk(r1, i1);
   }
+}
+
+template <int MU, int DIR, typename PsiF, typename UF>
+__device__ __forceinline__ void hop16p(cplx<float> acc[12], PsiF&& psi, UF&& u) {
+  cplx<float> g0[3], g1[3];
+  hop16p_g<MU, DIR>(psi, u, g0, g1);
   recon_acc<MU, DIR, float>(acc, g0, g1);
 }
 

@@ -93,6 +93,63 @@ __device__ __forceinline__ void blk_dir(const BlkCtx<T, SX, SG>& c, cplx<T> acc[
   __syncthreads();
 }
 
+// FP16 spinors and links: the same scheme with packed FP16 operands. The
+// half spinors are projected in packed FP16 arithmetic (one rounding to
+// FP16 per entry) and multiplied by the raw link entries with two-term dot
+// products accumulated in FP32 (exact products), so a hop is 36 dot
+// products, 12 packed adds and the FP32 rebuild. psi16 holds the site's
+// own spinor as packed (re, im) pairs.
+template <int MU, typename SX, typename SG>
+__device__ __forceinline__ void blk_dir16(const BlkCtx<float, SX, SG>& c, cplx<float> acc[12], const h2v psi16[12]) {
+  const Geom& g = c.g;
+  const int bvol = g.bvol, l = c.l;
+  const int st = g.lstride[MU];
+  const h2v* xsh = reinterpret_cast<const h2v*>(c.xsh);
+  const h2v* xr = reinterpret_cast<const h2v*>(c.xr);
+  const h2v* U = reinterpret_cast<const h2v*>(c.U);
+  cplx<float> g0[3], g1[3];
+  if (c.active) {
+    h2v w[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) w[e] = U[gauge_index(g, c.b, MU, e, l)];
+    auto wl = [&](int e) { return w[e]; };
+    // backward-hop half spinor for site n + mu: U_mu(n)^+ (1 + g_mu) psi(n)
+    hop16p_g<MU, -1>([&](int k) { return psi16[k]; }, wl, g0, g1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c.pb[a * bvol + l] = g0[a];
+      c.pb[(3 + a) * bvol + l] = g1[a];
+    }
+    // forward hop: (1 - g_mu) U_mu(n) psi(n + mu)
+    if (c.lc[MU] < g.B[MU] - 1) {
+      hop16p<MU, +1>(acc, [&](int k) { return xsh[k * bvol + l + st]; }, wl);
+    } else {
+      int c2[4] = {c.bc[0], c.bc[1], c.bc[2], c.bc[3]};
+      c2[MU] = (c.bc[MU] + 1 == g.N[MU]) ? 0 : c.bc[MU] + 1;
+      const int nb = encode_block(g, c2), nl = l - (g.B[MU] - 1) * st;
+      hop16p<MU, +1>(acc, [&](int k) { return xr[spinor_index(g, nb, k, nl)]; }, wl);
+    }
+  }
+  __syncthreads();
+  if (c.active) {
+    if (c.lc[MU] > 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        g0[a] = c.pb[a * bvol + l - st];
+        g1[a] = c.pb[(3 + a) * bvol + l - st];
+      }
+      recon_acc<MU, -1, float>(acc, g0, g1);
+    } else {
+      int c2[4] = {c.bc[0], c.bc[1], c.bc[2], c.bc[3]};
+      c2[MU] = (c.bc[MU] == 0) ? g.N[MU] - 1 : c.bc[MU] - 1;
+      const int nb = encode_block(g, c2), nl = l + (g.B[MU] - 1) * st;
+      hop16p<MU, -1>(acc, [&](int k) { return xr[spinor_index(g, nb, k, nl)]; },
+                     [&](int e) { return U[gauge_index(g, nb, MU, e, nl)]; });
+    }
+  }
+  __syncthreads();
+}
+
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 // per-right-hand-side gate and device-side mass (both optional)
@@ -126,10 +183,15 @@ __global__ void __launch_bounds__(MAXT)
   int bc[4], lc[4] = {0, 0, 0, 0};
   decode_block(g, b, bc);
   cplx<T> psi[12], acc[12];
+  // FP16 spinors and links without the clover term: packed FP16 hops
+  constexpr bool P16 = std::is_same<SX, s16>::value && std::is_same<SG, s16>::value &&
+                       std::is_same<T, float>::value && !CLOV;
+  h2v psi16[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     psi[k] = mk<T>(0, 0);
     acc[k] = mk<T>(0, 0);
+    psi16[k] = h2v{0, 0};
   }
   if (active) {
     decode_local(g, l, lc);
@@ -138,14 +200,22 @@ __global__ void __launch_bounds__(MAXT)
       const SX v = xr[spinor_index(g, b, k, l)];
       xsh[k * g.bvol + l] = v;
       psi[k] = storage_traits<SX>::template load<T>(v);
+      if constexpr (P16) psi16[k] = __builtin_bit_cast(h2v, v);
     }
   }
   __syncthreads();
   const BlkCtx<T, SX, SG> c{g, b, l, active, bc, lc, xr, xsh, pb, U};
-  blk_dir<0>(c, acc, psi);
-  blk_dir<1>(c, acc, psi);
-  blk_dir<2>(c, acc, psi);
-  blk_dir<3>(c, acc, psi);
+  if constexpr (P16) {
+    blk_dir16<0>(c, acc, psi16);
+    blk_dir16<1>(c, acc, psi16);
+    blk_dir16<2>(c, acc, psi16);
+    blk_dir16<3>(c, acc, psi16);
+  } else {
+    blk_dir<0>(c, acc, psi);
+    blk_dir<1>(c, acc, psi);
+    blk_dir<2>(c, acc, psi);
+    blk_dir<3>(c, acc, psi);
+  }
   if (active) {
     const T half = (T)0.5;
     if constexpr (CLOV) {

@@ -78,8 +78,10 @@ namespace {
 // request it takes has the same lattice, block and clover presence: the new
 // links are loaded into the same buffers and the captured cycles are
 // replayed (the solver keeps them for equal parameters and RHS count).
-// Otherwise, and whenever the slot goes idle, the field is freed, so the
-// memory the slot holds is always that of the request it is charged for.
+// Otherwise, and whenever the slot goes idle, the field is freed. While the
+// slot holds the field between requests, the footprint of the request that
+// made it stays charged to the budget, so the other slots never count on
+// that memory; the slot's next request takes the charge over.
 struct SlotField {
   dw_field f = nullptr;
   int L[4] = {}, block[4] = {};
@@ -103,6 +105,14 @@ void worker(dw_server s) {
   hipStream_t st = nullptr;
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
   SlotField held;
+  double held_fp = 0;  // footprint still charged for the held field
+  auto release_held = [&]() {
+    held.drop(st);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->in_use -= held_fp;
+    held_fp = 0;
+    s->cv.notify_all();
+  };
   while (true) {
     std::shared_ptr<Req> rq;
     {
@@ -113,32 +123,36 @@ void worker(dw_server s) {
       // backfilled requests never delay the head's admission for memory.
       // The head always fits once none run (submit checked it against the
       // whole budget), so the queue drains, also after stop.
+      // This slot's own held charge counts as free for its next request
+      // (the held field is reused or freed before anything new is made).
       size_t pick = 0;
       auto admissible = [&]() {
         if (s->queue.empty()) return false;
+        const double used = s->in_use - held_fp;
         const double head = (double)s->queue.front()->footprint;
-        if (s->in_use + head <= s->budget) {
+        if (used + head <= s->budget) {
           pick = 0;
           return true;
         }
         for (size_t i = 1; i < s->queue.size(); ++i)
-          if (s->in_use + head + (double)s->queue[i]->footprint <= s->budget) {
+          if (used + head + (double)s->queue[i]->footprint <= s->budget) {
             pick = i;
             return true;
           }
         return false;
       };
       if (!admissible() && held.f) {
-        // going idle: give the held field back before waiting
+        // going idle: give the held field (and its charge) back before waiting
         lk.unlock();
-        held.drop(st);
+        release_held();
         lk.lock();
       }
       s->cv.wait(lk, [&] { return admissible() || (s->stop && s->queue.empty()); });
       if (s->queue.empty()) break;
       rq = s->queue[pick];
       s->queue.erase(s->queue.begin() + (long)pick);
-      s->in_use += (double)rq->footprint;
+      s->in_use += (double)rq->footprint - held_fp;
+      held_fp = 0;
       rq->state = DW_REQ_RUNNING;
       rq->t_start = now_s();
     }
@@ -188,14 +202,16 @@ void worker(dw_server s) {
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      s->in_use -= (double)rq->footprint;
+      // a field kept for the next request keeps its charge
+      if (held.f) held_fp = (double)rq->footprint;
+      else s->in_use -= (double)rq->footprint;
       rq->t_end = now_s();
       rq->state = (status == DW_OK || status == DW_ENOTCONV) ? DW_REQ_DONE : DW_REQ_FAILED;
       rq->err = err;
     }
     s->cv.notify_all();
   }
-  held.drop(st);
+  release_held();
   if (have_stream) (void)hipStreamDestroy(st);
 }
 
