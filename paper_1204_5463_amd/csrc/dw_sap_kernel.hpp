@@ -214,6 +214,21 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
     for (int w = 0; w < nw; ++w) rr0 += red[6 * nw + w];
     rr = rr0;
   }
+  // FP16 links without the clover term on 4^4 blocks: the lane's own x, y and
+  // z links stay in registers through the MR steps; the backward hops read the
+  // neighbour's links from the lane 1, 4 or 16 below (a wave holds one t slice
+  // of the block, x fastest), so an MR step loads only the t links. This cuts
+  // the step's link traffic, which would otherwise come from beyond the L2
+  // (the links of the blocks in flight exceed it), to a quarter.
+  constexpr int NREG = (BS == 4 && L16 && P16 && !CLOV && !LDSL) ? 3 : 0;
+  using XW = std::conditional_t<(NREG > 0), h2v, int>;
+  XW ux[NREG > 0 ? NREG : 1][9];
+  if constexpr (NREG > 0) {
+#pragma unroll
+    for (int d = 0; d < NREG; ++d)
+#pragma unroll
+      for (int e = 0; e < 9; ++e) ux[d][e] = u_blk(d, e, l);
+  }
   for (int it = 0; it < nmr; ++it) {
     if (adapt && rr <= red2 * rr0) break;  // uniform over the workgroup
     __syncthreads();  // rho (and staged links) visible to the whole block
@@ -224,7 +239,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
       // losing occupancy (16-bit links, no clover term)
       constexpr bool AHEAD = BS > 0 && L16 && !CLOV;
       if constexpr (AHEAD && P16)
-        hop_sum_block_unrolled<T, h2v, BS>(l, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk, p);
+        hop_sum_block_unrolled<T, h2v, BS, NREG>(l, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,
+                                                 p, reinterpret_cast<const h2v(*)[9]>(ux));
       else if constexpr (AHEAD)
         hop_sum_block_unrolled<T, LK, BS>(l, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk, p);
       else if constexpr (P16)

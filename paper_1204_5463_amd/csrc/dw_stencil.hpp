@@ -16,6 +16,7 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "dw_geom.hpp"
 #include "dw_types.hpp"
@@ -454,9 +455,28 @@ __device__ __forceinline__ void hop_sum_staged(const Geom& g, int b, int l, cons
   }
 }
 
-// One direction of hop_sum_block_unrolled (below).
-template <int MU, int BS, typename T, typename SG, typename XB, typename UB, typename W>
-__device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk, cplx<T> acc[12], W wf[9]) {
+// The value of a 32-bit register in the lane S below (S = 1, 2, 4 or 8),
+// within rows of 16 lanes (DPP row shift; the first S lanes of a row get 0).
+template <int S, typename W>
+__device__ __forceinline__ W lane_below(W v) {
+  static_assert(sizeof(W) == 4, "one register");
+  if constexpr (S <= 15) {
+    return __builtin_bit_cast(W, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 + S, 0xF, 0xF, false));
+  } else {
+    // across rows: the LDS crossbar's backward permute (no LDS memory used)
+    const int lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return __builtin_bit_cast(W, __builtin_amdgcn_ds_bpermute(((lane - S) & 63) * 4, __builtin_bit_cast(int, v)));
+  }
+}
+
+// One direction of hop_sum_block_unrolled (below). Directions MU < NREG take
+// their links from registers (ux[MU], the lane's own site's links, held across
+// calls): the forward hop uses them directly and the backward hop those of the
+// lane st below (the site n - mu, in the same 16-lane row for x and y of 4^4
+// blocks).
+template <int MU, int BS, int NREG, typename T, typename SG, typename XB, typename UB, typename W>
+__device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk, cplx<T> acc[12], W wf[9],
+                                                   const W (*ux)[9]) {
   constexpr int LB = ilog2(BS);
   constexpr int st = 1 << (LB * MU);
   const int lcm = (l >> (LB * MU)) & (BS - 1);
@@ -465,8 +485,13 @@ __device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk
   // keep each direction's loads inside its own stretch of code (hoisted,
   // the next directions' links would not fit the register budget)
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (MU < NREG) {
 #pragma unroll
-  for (int e = 0; e < 9; ++e) wb[e] = u_blk(MU, e, ub);
+    for (int e = 0; e < 9; ++e) wb[e] = lane_below<st>(ux[MU][e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) wb[e] = u_blk(MU, e, ub);
+  }
   auto do_hop = [&](auto dirc, auto&& psi, auto&& u) {
     constexpr int DIR = decltype(dirc)::value;
     if constexpr (std::is_same<SG, h2v>::value) hop16p<MU, DIR>(acc, psi, u);
@@ -477,7 +502,7 @@ __device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk
     do_hop(std::integral_constant<int, 1>{}, [&](int k) { return xin_blk(l + st, k); }, [&](int e) { return wf[e]; });
   if constexpr (MU < 3) {
 #pragma unroll
-    for (int e = 0; e < 9; ++e) wf[e] = u_blk(MU + 1, e, l);
+    for (int e = 0; e < 9; ++e) wf[e] = MU + 1 < NREG ? ux[MU + 1][e] : u_blk(MU + 1, e, l);
   }
   if (lcm > 0)
     do_hop(std::integral_constant<int, -1>{}, [&](int k) { return xin_blk(l - st, k); }, [&](int e) { return wb[e]; });
@@ -493,19 +518,20 @@ __device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk
 // Directions are unrolled at compile time: every hop is a straight-line
 // body under its lane mask (no switch over the hop index), so the
 // accumulator stays in the same registers from hop to hop.
-template <typename T, typename SG, int BS, typename XB, typename UB>
-__device__ __forceinline__ void hop_sum_block_unrolled(int l, XB&& xin_blk, UB&& u_blk, cplx<T> acc[12]) {
+template <typename T, typename SG, int BS, int NREG = 0, typename XB, typename UB,
+          typename W = std::remove_cv_t<std::remove_reference_t<decltype(std::declval<UB>()(0, 0, 0))>>>
+__device__ __forceinline__ void hop_sum_block_unrolled(int l, XB&& xin_blk, UB&& u_blk, cplx<T> acc[12],
+                                                       const W (*ux)[9] = nullptr) {
   static_assert(BS > 0 && (BS & (BS - 1)) == 0, "compile-time block side must be a power of two");
-  using W = decltype(u_blk(0, 0, 0));
 #pragma unroll
   for (int i = 0; i < 12; ++i) acc[i] = mk<T>(0, 0);
   W wf[9];
 #pragma unroll
-  for (int e = 0; e < 9; ++e) wf[e] = u_blk(0, e, l);
-  block_dir_unrolled<0, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
-  block_dir_unrolled<1, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
-  block_dir_unrolled<2, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
-  block_dir_unrolled<3, BS, T, SG>(l, xin_blk, u_blk, acc, wf);
+  for (int e = 0; e < 9; ++e) wf[e] = NREG > 0 ? ux[0][e] : u_blk(0, e, l);
+  block_dir_unrolled<0, BS, NREG, T, SG>(l, xin_blk, u_blk, acc, wf, ux);
+  block_dir_unrolled<1, BS, NREG, T, SG>(l, xin_blk, u_blk, acc, wf, ux);
+  block_dir_unrolled<2, BS, NREG, T, SG>(l, xin_blk, u_blk, acc, wf, ux);
+  block_dir_unrolled<3, BS, NREG, T, SG>(l, xin_blk, u_blk, acc, wf, ux);
 }
 
 // Full hopping sum (faces included) for compile-time BS^4 blocks: each hop's
