@@ -220,8 +220,8 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
   // of the block, x fastest), so an MR step loads only the t links. This cuts
   // the step's link traffic, which would otherwise come from beyond the L2
   // (the links of the blocks in flight exceed it), to a quarter.
-  constexpr int NREG = (BS == 4 && L16 && P16 && !CLOV && !LDSL) ? 3 : 0;
-  using XW = std::conditional_t<(NREG > 0), h2v, int>;
+  constexpr int NREG = (BS == 4 && L16 && !CLOV && !LDSL) ? 4 : 0;
+  using XW = std::conditional_t<(NREG > 0), decltype(u_blk(0, 0, 0)), int>;
   XW ux[NREG > 0 ? NREG : 1][9];
   if constexpr (NREG > 0) {
 #pragma unroll
@@ -240,9 +240,10 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
       constexpr bool AHEAD = BS > 0 && L16 && !CLOV;
       if constexpr (AHEAD && P16)
         hop_sum_block_unrolled<T, h2v, BS, NREG>(l, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,
-                                                 p, reinterpret_cast<const h2v(*)[9]>(ux));
+                                                 p, reinterpret_cast<const XW(*)[9]>(ux));
       else if constexpr (AHEAD)
-        hop_sum_block_unrolled<T, LK, BS>(l, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk, p);
+        hop_sum_block_unrolled<T, LK, BS, NREG>(l, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk, p,
+                                                reinterpret_cast<const XW(*)[9]>(ux));
       else if constexpr (P16)
         hop_sum_staged<T, false, h2v, BS>(
             g, b, l, bc, lc, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,

@@ -485,7 +485,7 @@ __device__ __forceinline__ void block_dir_unrolled(int l, XB& xin_blk, UB& u_blk
   // keep each direction's loads inside its own stretch of code (hoisted,
   // the next directions' links would not fit the register budget)
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (MU < NREG) {
+  if constexpr (MU < NREG && MU < 3) {
 #pragma unroll
     for (int e = 0; e < 9; ++e) wb[e] = lane_below<st>(ux[MU][e]);
   } else {
