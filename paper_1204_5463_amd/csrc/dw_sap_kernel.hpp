@@ -138,17 +138,29 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
     if constexpr (L16) return link16<SG>::raw(p);
     else return ld<T>(p);
   };
-  // 16-bit links from memory: buffer loads with the block's links as the
-  // resource, the entry's offset in a scalar register and the lane's site in
-  // one vector register (no per-entry 64-bit address arithmetic)
+  // links from memory: buffer loads with the block's links as the resource,
+  // the entry's offset in a scalar register and the lane's site in one vector
+  // register (no per-entry 64-bit address arithmetic)
   [[maybe_unused]] const __amdgpu_buffer_rsrc_t ub_rsrc =
       __builtin_amdgcn_make_buffer_rsrc((void*)Ub, (short)0, 36 * bvol * (int)sizeof(SG), 0x00020000);
   auto u_blk = [&](int mu, int e, int ls) {
-    if constexpr (LDSL) return load_link(lks + (mu * 9 + e) * bvol + ls);
-    else if constexpr (L16 && sizeof(SG) == 4)
-      return __builtin_bit_cast(decltype(load_link(Ub)),
-                                __builtin_amdgcn_raw_buffer_load_b32(ub_rsrc, ls * 4, (mu * 9 + e) * bvol * 4, 0));
-    else return load_link(Ub + (mu * 9 + e) * bvol + ls);
+    constexpr int sz = (int)sizeof(SG);
+    const int vo = ls * sz, so = (mu * 9 + e) * bvol * sz;
+    if constexpr (LDSL) {
+      return load_link(lks + (mu * 9 + e) * bvol + ls);
+    } else if constexpr (L16 && sz == 4) {
+      return __builtin_bit_cast(decltype(load_link(Ub)), __builtin_amdgcn_raw_buffer_load_b32(ub_rsrc, vo, so, 0));
+    } else if constexpr (std::is_same<SG, s32>::value && std::is_same<T, float>::value) {
+      typedef float f2 __attribute__((ext_vector_type(2)));
+      const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ub_rsrc, vo, so, 0));
+      return mk<T>(v.x, v.y);
+    } else if constexpr (std::is_same<SG, s64>::value && std::is_same<T, double>::value) {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      const d2 v = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(ub_rsrc, vo, so, 0));
+      return mk<T>(v.x, v.y);
+    } else {
+      return load_link(Ub + (mu * 9 + e) * bvol + ls);
+    }
   };
   auto u_halo = [&](int nb, int mu, int e, int nl) {
     return load_link(U + ((long long)nb * 36 + mu * 9 + e) * bvol + nl);
@@ -237,13 +249,15 @@ __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(sap_w
     if (active) {
       // links loaded one hop ahead where the registers allow it without
       // losing occupancy (16-bit links, no clover term)
-      constexpr bool AHEAD = BS > 0 && L16 && !CLOV;
+      constexpr bool AHEAD = BS > 0 && !CLOV;
       if constexpr (AHEAD && P16)
         hop_sum_block_unrolled<T, h2v, BS, NREG>(l, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,
                                                  p, reinterpret_cast<const XW(*)[9]>(ux));
-      else if constexpr (AHEAD)
+      else if constexpr (AHEAD && NREG > 0)
         hop_sum_block_unrolled<T, LK, BS, NREG>(l, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk, p,
                                                 reinterpret_cast<const XW(*)[9]>(ux));
+      else if constexpr (AHEAD)
+        hop_sum_block_unrolled<T, LK, BS>(l, [&](int nl, int k) { return rho_s[k * bvol + nl]; }, u_blk, p);
       else if constexpr (P16)
         hop_sum_staged<T, false, h2v, BS>(
             g, b, l, bc, lc, [&](int nl, int k) { return rho16[k * bvol + nl]; }, u_blk,
