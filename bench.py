@@ -289,13 +289,29 @@ def serve(args):
         reqs.append(dict(arrival=t, lattice=n, nrhs=nrhs, m0=mc[n][0] + delta, seed=3000 + 100 * i))
     log(f"[serve] {len(reqs)} requests over {t:.2f} s of arrivals, {sum(r['nrhs'] for r in reqs)} RHS")
 
-    def rhs_of(r):
-        # the request's right-hand sides, made on the device when it is sent
-        # (seeded Gaussian entries; the serial baseline draws the same)
+    # The client's request buffers (right-hand sides and solutions) come from
+    # one preallocated pool of slots + 2 buffer pairs, each large enough for the
+    # largest request, so that the client's device memory stays fixed (a
+    # caching allocator fed requests of many sizes would keep growing into the
+    # memory the server's budget counts on).
+    shp_of = {n: synth.lattice_shape(SERVE_LATTICES[n]) + (4, 3) for n in names}
+    big = max(cap[n] * math.prod(shp_of[n]) for n in names)
+    nbuf = args.slots + 2
+    pool = torch.empty((nbuf, 2, big), dtype=torch.complex128, device="cuda") if args.serve_part != "fp64" else None
+    free_bufs = list(range(nbuf))
+
+    def rhs_into(r, out):
+        # the request's right-hand sides, made on the device when it is sent:
+        # seeded Gaussian real and imaginary parts of variance 1/2 (the serial
+        # baseline draws the same)
         gen = torch.Generator(device="cuda")
         gen.manual_seed(r["seed"])
-        shp = (r["nrhs"],) + synth.lattice_shape(SERVE_LATTICES[r["lattice"]]) + (4, 3)
-        return torch.randn(shp, dtype=torch.complex128, device="cuda", generator=gen)
+        torch.view_as_real(out).normal_(0.0, math.sqrt(0.5), generator=gen)
+        return out
+
+    def rhs_of(r):
+        shp = (r["nrhs"],) + shp_of[r["lattice"]]
+        return rhs_into(r, torch.empty(shp, dtype=torch.complex128, device="cuda"))
 
     ctx = P.Context(0)
     # warm the kernels of every lattice once (untimed)
@@ -330,22 +346,28 @@ def serve(args):
         # slots + 2 unfinished ones (their inputs and outputs then go to
         # device memory), as a client would queue them; latency runs from
         # the arrival time.
-        srv = P.Server(ctx, slots=args.slots, queue_capacity=args.slots + 2)
-        pending, done, lat = {}, {}, [0.0] * len(reqs)
+        srv = P.Server(ctx, slots=args.slots, queue_capacity=nbuf)
+        pending, done, lat, buf_of = {}, {}, [0.0] * len(reqs), {}
         t0 = time.perf_counter()
         i = 0
         while i < len(reqs) or pending:
             now = time.perf_counter() - t0
-            while i < len(reqs) and reqs[i]["arrival"] <= now and len(pending) < args.slots + 2:
+            while i < len(reqs) and reqs[i]["arrival"] <= now and free_bufs:
                 r = reqs[i]
-                tk = srv.submit(SERVE_LATTICES[r["lattice"]], (4, 4, 4, 4), r["m0"], fields[r["lattice"]], rhs_of(r),
-                                params(P.DW_PREC_F16, graphs=True))
+                shp = (r["nrhs"],) + shp_of[r["lattice"]]
+                nel = math.prod(shp)
+                q = free_bufs.pop()
+                b = rhs_into(r, pool[q, 0, :nel].view(shp))
+                tk = srv.submit(SERVE_LATTICES[r["lattice"]], (4, 4, 4, 4), r["m0"], fields[r["lattice"]], b,
+                                params(P.DW_PREC_F16, graphs=True), x=pool[q, 1, :nel].view(shp))
                 pending[tk] = i
+                buf_of[tk] = q
                 i += 1
             for tk in list(pending):
                 out = srv.poll(tk)
                 if out is not None:
                     x, st, tm = out
+                    free_bufs.append(buf_of.pop(tk))
                     k = pending.pop(tk)
                     fin = time.perf_counter() - t0
                     done[k] = (st, tm, fin)

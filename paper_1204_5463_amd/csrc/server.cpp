@@ -44,6 +44,16 @@ void* async_alloc(size_t bytes, hipStream_t s, void*) {
 }
 void async_free(void* p, hipStream_t s, void*) { (void)hipFreeAsync(p, s); }
 
+// Memory freed on one slot's stream returns to the device's pool of the
+// stream-ordered allocator; released to the device once the stream has been
+// synchronised, it is free for the other slots too, so that the memory the
+// admission counts as free is free (kept in the pool, another slot could not
+// always reuse it and would grow the pool beyond the budget).
+void trim_pool(int device) {
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) (void)hipMemPoolTrimTo(pool, 0);
+}
+
 struct Req {
   uint64_t ticket = 0;
   dw_request r{};
@@ -92,11 +102,13 @@ struct SlotField {
       if (L[i] != r.L[i] || block[i] != r.block[i]) return false;
     return true;
   }
-  void drop(hipStream_t st) {
+  void drop(hipStream_t st, int device) {
     if (!f) return;
     (void)hipStreamSynchronize(st);
     dw_field_destroy(f);
     f = nullptr;
+    (void)hipStreamSynchronize(st);
+    trim_pool(device);
   }
 };
 
@@ -107,7 +119,7 @@ void worker(dw_server s) {
   SlotField held;
   double held_fp = 0;  // footprint still charged for the held field
   auto release_held = [&]() {
-    held.drop(st);
+    held.drop(st, s->ictx->device);
     std::lock_guard<std::mutex> lk(s->mu);
     s->in_use -= held_fp;
     held_fp = 0;
@@ -163,10 +175,10 @@ void worker(dw_server s) {
         status = field_reload(held.f, rq->r.U, rq->r.csw, st);
         if (status != DW_OK) {
           err = dw_last_error();
-          held.drop(st);
+          held.drop(st, s->ictx->device);
         }
       } else {
-        held.drop(st);
+        held.drop(st, s->ictx->device);
         dw_field f = nullptr;
         status = dw_field_create(s->ictx, rq->r.L, rq->r.block, rq->r.U, st, &f);
         if (status == DW_OK && rq->r.csw != 0.0) {
@@ -195,10 +207,11 @@ void worker(dw_server s) {
         status = fgmresdr_solve(held.f, rq->r.m0, &prm, rq->r.b, rq->r.x, rq->r.nrhs, rq->stats.data(), st);
         if (status != DW_OK && status != DW_ENOTCONV) {
           err = dw_last_error();
-          held.drop(st);
+          held.drop(st, s->ictx->device);
         }
       }
       (void)hipStreamSynchronize(st);
+      trim_pool(s->ictx->device);
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
