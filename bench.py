@@ -40,8 +40,12 @@ WORKLOADS = {
     # s = 8, nMR = 9, the optimum of a search capped at s = 8, needs 37
     # iterations and 6% more time; the starting point s = 2, nMR = 5 needs
     # 152 iterations and 2.5x the time
+    # The mass: 0.005 above the critical mass estimated on the 16^3x32 field of
+    # the same eps (no estimate converges on 32^3x64 itself); at this distance
+    # the solve makes one deflated restart (0.01 above: 25 iterations in one
+    # cycle; 0.002: 45; 0: 64)
     "32^3x64": dict(L=(32, 32, 32, 64), eps=0.7, seed=0,
-                    mass=(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
+                    mass=(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.005),
                     block=(4, 4, 4, 4), ncycles=13, nmr=8, storage="f16", m=30, k=12),
     "16^3x32": dict(L=(16, 16, 16, 32), eps=0.6, seed=0, mass=(("16^3x32_eps0.6", "12^4_eps0.6"), 0.001),
                     block=(4, 4, 4, 4), ncycles=2, nmr=5, storage="f32", m=30, k=10),
@@ -53,7 +57,7 @@ WORKLOADS = {
     # tuning (the starting point 8x4x4x4, s = 2, nMR = 5 takes 168 iterations
     # and 2.6x the time)
     "32^3x64x12": dict(L=(32, 32, 32, 64), eps=0.7, seed=0,
-                       mass=(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.01),
+                       mass=(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.005),
                        block=(4, 4, 4, 4), ncycles=13, nmr=8, storage="f16", m=20, k=8, nrhs=12, rhs="point"),
     # the same lattice with the clover term (c_sw = 1.9, as in the paper's
     # experiments), near the critical mass of the clover operator; the SAP
@@ -508,7 +512,7 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
     ap.add_argument("--max-rhs", type=int, default=12)
-    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--serve-cycles", type=int, default=6, help="serving: SAP cycles per application")
     ap.add_argument("--serve-part", choices=("both", "mixed", "fp64"), default="both",
                     help="serving: run the server stream, the serial all-FP64 baseline, or both")
