@@ -378,11 +378,23 @@ def serve(args):
                     lat[k] = fin - reqs[k]["arrival"]
                     r = reqs[k]
                     log(f"[serve] request {k} {r['lattice']} nrhs={r['nrhs']} done: "
-                        f"{max(s.iterations for s in st)} it, latency {lat[k]:.3f} s")
+                        f"{max(s.iterations for s in st)} it (per RHS {[s.iterations for s in st]}), "
+                        f"service {tm['running']:.3f} s, latency {lat[k]:.3f} s")
                     del x
             time.sleep(2e-4)
         makespan = time.perf_counter() - t0
         srv.close()
+        # service time (admitted to done) per lattice: the sum over requests
+        # against slots x makespan gives the slots' occupancy
+        svc = {}
+        for k in range(len(reqs)):
+            n = reqs[k]["lattice"]
+            svc.setdefault(n, []).append(done[k][1]["running"])
+        line.update({
+            "service_s_per_lattice": {n: {"requests": len(v), "mean": round(sum(v) / len(v), 4),
+                                          "sum": round(sum(v), 2)} for n, v in svc.items()},
+            "slot_occupancy": round(sum(sum(v) for v in svc.values()) / (args.slots * makespan), 3),
+        })
         line.update({
             "value": round(len(reqs) / makespan, 4),
             "makespan_s": round(makespan, 3),
@@ -409,6 +421,9 @@ def serve(args):
             svc.append(time.perf_counter() - ts)
             conv64 = conv64 and all(x.converged for x in st)
             log(f"[serve] serial {k} {r['lattice']} nrhs={r['nrhs']}: {svc[-1]:.3f} s")
+        svc64 = {}
+        for r, sv in zip(reqs, svc):
+            svc64.setdefault(r["lattice"], []).append(sv)
         fin, lat64 = 0.0, []
         for r, sv in zip(reqs, svc):
             fin = max(fin, r["arrival"]) + sv
@@ -416,6 +431,8 @@ def serve(args):
         line["serial_fp64"] = {"requests_per_s": round(len(reqs) / fin, 4) if fin > 0 else None,
                                "rhs_solves_per_s": round(rhs_total / fin, 4) if fin > 0 else None,
                                "busy_s": round(sum(svc), 3),
+                               "service_s_per_lattice": {n: {"requests": len(v), "mean": round(sum(v) / len(v), 4),
+                                                             "sum": round(sum(v), 2)} for n, v in svc64.items()},
                                "p50_latency_ms": round(1e3 * pct(lat64, 0.5), 1),
                                "p99_latency_ms": round(1e3 * pct(lat64, 0.99), 1),
                                "all_converged": conv64}

@@ -60,6 +60,9 @@ struct dw_field_s {
   // solver workspace and captured cycles kept for the next solve (DW_SOLVE_GRAPHS)
   void* solver_cache = nullptr;
   void (*solver_cache_free)(void*) = nullptr;
+  // set by the server: the admission has reserved the memory of the whole
+  // request, so a solve keeps all its right-hand sides in one batch
+  bool memory_reserved = false;
 };
 
 namespace dw {

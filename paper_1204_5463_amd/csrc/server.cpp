@@ -37,22 +37,99 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-void* async_alloc(size_t bytes, hipStream_t s, void*) {
-  void* p = nullptr;
-  if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
-  return p;
-}
-void async_free(void* p, hipStream_t s, void*) { (void)hipFreeAsync(p, s); }
+// Device memory of the server's requests: a caching allocator shared by the
+// slots. A block freed on a slot's stream waits in that stream's pending list
+// until the slot has synchronised its stream (at the end of each request and
+// after dropping a field); it then joins the free list, from which any slot
+// takes it again when its size fits (at most a quarter larger). Requests of
+// one lattice and RHS count therefore run on the same blocks, mapped once
+// (allocating and freeing them through the driver or the stream-ordered pool
+// for every request fragments the device memory: later requests ran up to
+// three times slower). When the device has no room for a new block, the free
+// blocks are released first. The admission budget counts only the requests'
+// own footprints; free cached blocks are released on demand.
+struct BlockCache {
+  struct Block {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::mutex mu;
+  std::vector<Block> free_blocks;
+  std::unordered_map<void*, size_t> live;
+  std::unordered_map<hipStream_t, std::vector<Block>> pending;
 
-// Memory freed on one slot's stream returns to the device's pool of the
-// stream-ordered allocator; released to the device once the stream has been
-// synchronised, it is free for the other slots too, so that the memory the
-// admission counts as free is free (kept in the pool, another slot could not
-// always reuse it and would grow the pool beyond the budget).
-void trim_pool(int device) {
-  hipMemPool_t pool = nullptr;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) (void)hipMemPoolTrimTo(pool, 0);
-}
+  void release_free() {  // with mu held
+    for (auto& b : free_blocks) (void)hipFree(b.p);
+    free_blocks.clear();
+  }
+  void* alloc(size_t bytes, hipStream_t s) {
+    void* p = try_alloc(bytes);
+    if (p) return p;
+    // no room: the blocks this stream freed are reusable once it has drained
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone &&
+        hipStreamSynchronize(s) == hipSuccess) {
+      retire(s);
+      std::lock_guard<std::mutex> lk(mu);
+      release_free();
+    }
+    (void)hipGetLastError();
+    return try_alloc(bytes);
+  }
+  void* try_alloc(size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    size_t best = SIZE_MAX;
+    int pick = -1;
+    for (int i = 0; i < (int)free_blocks.size(); ++i) {
+      const Block& b = free_blocks[i];
+      if (b.bytes >= bytes && b.bytes - bytes <= bytes / 4 && b.bytes < best) {
+        best = b.bytes;
+        pick = i;
+      }
+    }
+    if (pick >= 0) {
+      const Block b = free_blocks[pick];
+      free_blocks.erase(free_blocks.begin() + pick);
+      live[b.p] = b.bytes;
+      return b.p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      release_free();
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    live[p] = bytes;
+    return p;
+  }
+  void free(void* p, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    pending[s].push_back(Block{p, it->second});
+    live.erase(it);
+  }
+  // the stream s has been synchronised: its freed blocks are reusable
+  void retire(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = pending.find(s);
+    if (it == pending.end()) return;
+    free_blocks.insert(free_blocks.end(), it->second.begin(), it->second.end());
+    pending.erase(it);
+  }
+  ~BlockCache() {
+    for (auto& b : free_blocks) (void)hipFree(b.p);
+    for (auto& kv : pending)
+      for (auto& b : kv.second) (void)hipFree(b.p);
+    for (auto& kv : live) (void)hipFree(kv.first);
+  }
+};
+
+void* cache_alloc(size_t bytes, hipStream_t s, void* user) { return static_cast<BlockCache*>(user)->alloc(bytes, s); }
+void cache_free(void* p, hipStream_t s, void* user) { static_cast<BlockCache*>(user)->free(p, s); }
 
 struct Req {
   uint64_t ticket = 0;
@@ -68,7 +145,8 @@ struct Req {
 
 struct dw_server_s {
   dw_ctx user_ctx = nullptr;
-  dw_ctx ictx = nullptr;  // stream-ordered allocator
+  dw_ctx ictx = nullptr;  // allocates through `blocks`
+  std::unique_ptr<BlockCache> blocks;
   dw_server_params p{};
   double budget = 0;
   std::mutex mu;
@@ -102,13 +180,13 @@ struct SlotField {
       if (L[i] != r.L[i] || block[i] != r.block[i]) return false;
     return true;
   }
-  void drop(hipStream_t st, int device) {
+  void drop(hipStream_t st, BlockCache* blocks) {
     if (!f) return;
     (void)hipStreamSynchronize(st);
     dw_field_destroy(f);
     f = nullptr;
     (void)hipStreamSynchronize(st);
-    trim_pool(device);
+    blocks->retire(st);
   }
 };
 
@@ -119,7 +197,7 @@ void worker(dw_server s) {
   SlotField held;
   double held_fp = 0;  // footprint still charged for the held field
   auto release_held = [&]() {
-    held.drop(st, s->ictx->device);
+    held.drop(st, s->blocks.get());
     std::lock_guard<std::mutex> lk(s->mu);
     s->in_use -= held_fp;
     held_fp = 0;
@@ -175,10 +253,10 @@ void worker(dw_server s) {
         status = field_reload(held.f, rq->r.U, rq->r.csw, st);
         if (status != DW_OK) {
           err = dw_last_error();
-          held.drop(st, s->ictx->device);
+          held.drop(st, s->blocks.get());
         }
       } else {
-        held.drop(st, s->ictx->device);
+        held.drop(st, s->blocks.get());
         dw_field f = nullptr;
         status = dw_field_create(s->ictx, rq->r.L, rq->r.block, rq->r.U, st, &f);
         if (status == DW_OK && rq->r.csw != 0.0) {
@@ -192,6 +270,7 @@ void worker(dw_server s) {
           err = dw_last_error();
         }
         if (status == DW_OK) {
+          f->memory_reserved = true;  // the footprint charged covers the whole request
           held.f = f;
           for (int i = 0; i < 4; ++i) {
             held.L[i] = rq->r.L[i];
@@ -207,11 +286,11 @@ void worker(dw_server s) {
         status = fgmresdr_solve(held.f, rq->r.m0, &prm, rq->r.b, rq->r.x, rq->r.nrhs, rq->stats.data(), st);
         if (status != DW_OK && status != DW_ENOTCONV) {
           err = dw_last_error();
-          held.drop(st, s->ictx->device);
+          held.drop(st, s->blocks.get());
         }
       }
       (void)hipStreamSynchronize(st);
-      trim_pool(s->ictx->device);
+      s->blocks->retire(st);
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -254,12 +333,14 @@ dw_status dw_server_create(dw_ctx ctx, const dw_server_params* p, dw_server* out
   }
   *out = nullptr;
   DW_CHECK_HIP(hipSetDevice(ctx->device));
-  dw_allocator a{async_alloc, async_free, nullptr};
+  auto blocks = std::make_unique<BlockCache>();
+  dw_allocator a{cache_alloc, cache_free, blocks.get()};
   dw_ctx ictx = nullptr;
   DW_TRY(dw_ctx_create(ctx->device, &a, &ictx));
   dw_server s = new dw_server_s;
   s->user_ctx = ctx;
   s->ictx = ictx;
+  s->blocks = std::move(blocks);
   s->p = *p;
   if (p->budget_bytes > 0) {
     s->budget = p->budget_bytes;
@@ -287,8 +368,9 @@ dw_status dw_server_destroy(dw_server s) {
   }
   s->cv.notify_all();
   for (auto& t : s->workers) t.join();
+  (void)hipDeviceSynchronize();
   dw_ctx_destroy(s->ictx);
-  delete s;
+  delete s;  // frees the cached blocks after the context (whose last frees return blocks to it)
   return DW_OK;
 }
 

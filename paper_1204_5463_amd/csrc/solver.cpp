@@ -640,11 +640,20 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
   // most kMaxBatch (the per-RHS masks of a batch are 64 bits wide)
   size_t free_b = 0, total_b = 0;
   DW_CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
+  {
+    // memory that the stream-ordered allocator's pool holds unused is free too
+    hipMemPool_t pool = nullptr;
+    uint64_t res = 0, used = 0;
+    if (hipDeviceGetDefaultMemPool(&pool, f->ctx->device) == hipSuccess && pool &&
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &res) == hipSuccess &&
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemCurrent, &used) == hipSuccess && res > used)
+      free_b += (size_t)(res - used);
+  }
   const size_t per = bytes_per_rhs(n, P->m, P->sap.storage, basis_prec(P), zstore_prec(P));
   const bool reuse = graphs && cache && cache->W && cache->W->nr == nrhs && same_params(cache->W->P, *P) &&
                      cache->W->clover[0] == f->C[P->sap.storage] && cache->W->clover[1] == f->C[DW_PREC_F64];
   int nb = (int)std::max<size_t>(1, (size_t)(0.9 * (double)free_b) / per);
-  if (reuse) nb = nrhs;
+  if (reuse || f->memory_reserved) nb = nrhs;
   nb = std::min(nb, (int)nrhs);
   nb = std::min(nb, kMaxBatch);
   if (graphs && !reuse && cache) {
