@@ -307,8 +307,14 @@ dw_status dw_dense_restart(dw_ctx ctx, int32_t mm, int32_t k, const double* Hhat
  * only if it leaves room for the oldest waiting one); each slot runs its request
  * on its own HIP stream, so admitted requests overlap on the device, and
  * keeps the request's gauge copies and Krylov / deflation state on the
- * device until the request completes. Server memory is stream-ordered
- * (hipMallocAsync), independent of the context's allocator. */
+ * device until the request completes. Server memory comes from the server's
+ * own caching allocator (independent of the context's allocator): blocks a
+ * slot frees are reused by any slot once that slot's stream has drained, and
+ * free cached blocks are returned to the device when an allocation finds it
+ * full. A slot keeps the field of its last request (links, workspace and
+ * captured restart cycles) while its next request has the same lattice and
+ * block; the footprint of the request that made it stays charged until then.
+ * Every request runs on restart cycles captured as HIP graphs. */
 typedef struct dw_server_params {
   int32_t slots;           /* requests solved concurrently (>= 1) */
   int32_t queue_capacity;  /* queued, not yet admitted requests; solve_submit returns DW_EBUSY beyond */
