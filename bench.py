@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--mean-gap", type=float, default=0.05, help="mean inter-arrival time (s)")
     ap.add_argument("--max-rhs", type=int, default=12)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--serve-cycles", type=int, default=6, help="serving: SAP cycles per application")
     ap.add_argument("--serve-part", choices=("both", "mixed", "fp64"), default="both",
                     help="serving: run the server stream, the serial all-FP64 baseline, or both")
