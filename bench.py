@@ -6,7 +6,7 @@ A step is one complete solve D x = b to a true FP64 relative residual of
 1e-10 (every row of the method: SAP sweeps, FP64 operator, Arnoldi,
 least squares, deflated restarts, explicit residuals). The default
 workload is the 32^3 x 64 lattice with eps = 0.7 links at a near-critical
-mass, FP16-storage SAP (4^4 blocks, 8 cycles, 9 MR steps, as tuned) inside
+mass, FP16-storage SAP (4^4 blocks, 13 cycles, 8 MR steps, as tuned) inside
 FP64 FGMRES-DR(30, 12). The same solve with all-FP64 SAP is timed beside it, the
 Wilson-Dirac operator alone is timed at each storage precision, and the
 FP64 CPU oracle is timed on a bounded sample of the same work.
@@ -37,9 +37,9 @@ WORKLOADS = {
     # (4^4 blocks, 13 cycles, 8 MR steps) are the time-to-solution optimum
     # found by dw_autotune on this system (4^4 blocks, nMR 6..14, s 4..16;
     # an earlier search over all block shapes with extents 2/4/8 picked 4^4);
-    # s = 8, nMR = 9, the optimum of a search capped at s = 8, needs 37
-    # iterations and 6% more time; the starting point s = 2, nMR = 5 needs
-    # 152 iterations and 2.5x the time
+    # at m0 = m_c(12^4) + 0.01, s = 8, nMR = 9, the optimum of a search capped
+    # at s = 8, needed 37 iterations and 6% more time; the starting point
+    # s = 2, nMR = 5 needed 152 iterations and 2.5x the time
     # The mass: 0.005 above the critical mass estimated on the 16^3x32 field of
     # the same eps (no estimate converges on 32^3x64 itself); at this distance
     # the solve makes one deflated restart (0.01 above: 25 iterations in one
