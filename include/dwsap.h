@@ -115,9 +115,12 @@ typedef struct sap_params {
  *              workspace and the graphs stay with the field, so later solves
  *              with the same m, k, SAP parameters, flags and RHS count
  *              (any mass, tolerance, max_iter, restart_t and b) replay them
- *              too. dw_field_destroy, dw_field_set_clover or a solve with
- *              other parameters frees them. Used on a non-default stream with
- *              per-kernel timing off, else ignored.
+ *              too, and such a solve without graphs (flag clear, default
+ *              stream, or per-kernel timing on) reuses the workspace.
+ *              dw_field_destroy,
+ *              dw_field_set_clover or a solve with other parameters frees
+ *              them. Used on a non-default stream with per-kernel timing
+ *              off, else ignored.
  *              DW_SOLVE_V32: store the Krylov basis V in FP32 (the arithmetic
  *              stays FP64), which halves the Gram-Schmidt traffic; the
  *              Arnoldi relation then holds to FP32 accuracy and the explicit
@@ -259,8 +262,10 @@ dw_status sap_solve(dw_field field, double m0, const sap_params* sap, const doub
                     double* resid, hipStream_t stream);
 
 /* Solves D x = b by SAP-preconditioned FGMRES-DR(m, k) (Alg. 4) from x = 0
- * for nrhs right-hand sides (solved in lock-step, every SAP and stencil
- * launch covering all of them). Arnoldi, Hessenberg updates, harmonic Ritz
+ * for nrhs right-hand sides, solved in lock-step (every SAP and stencil
+ * launch covering the whole batch): all nrhs in one batch whenever their
+ * workspace can be allocated (up to 64), else in batches of as many as
+ * 90% of the free device memory holds. Arnoldi, Hessenberg updates, harmonic Ritz
  * deflation and the least-squares problems are FP64; the explicit residual
  * is computed in FP64 once per cycle and enters the least-squares right-hand
  * side (Section 4.7); the preconditioner runs at `params->sap.storage`.

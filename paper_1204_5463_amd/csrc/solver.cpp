@@ -578,7 +578,10 @@ struct Solver {
 };
 
 bool same_params(const fgmresdr_params& a, const fgmresdr_params& b) {
-  return a.m == b.m && a.k == b.k && a.shared_defl == b.shared_defl && a.flags == b.flags &&
+  // the graphs flag only says whether cycles are captured; the workspace and
+  // the captured cycles are the same either way
+  const int32_t fa = a.flags & ~DW_SOLVE_GRAPHS, fb = b.flags & ~DW_SOLVE_GRAPHS;
+  return a.m == b.m && a.k == b.k && a.shared_defl == b.shared_defl && fa == fb &&
          a.sap.ncycles == b.sap.ncycles && a.sap.nmr == b.sap.nmr && a.sap.storage == b.sap.storage &&
          a.sap.mr_reduction == b.sap.mr_reduction;
 }
@@ -636,6 +639,18 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
   // captured cycles need a stream that can be captured and no per-launch event timing
   const bool graphs = (P->flags & DW_SOLVE_GRAPHS) && stream != nullptr && !f->ctx->prof.on;
   SolverCache* cache = static_cast<SolverCache*>(f->solver_cache);
+  // a workspace kept by an earlier solve with captured cycles serves this
+  // solve too (captured or not) when it was made for the same shape; else it
+  // goes before the free memory is counted
+  const bool reuse = cache && cache->W && cache->W->nr == nrhs && same_params(cache->W->P, *P) &&
+                     cache->W->clover[0] == f->C[P->sap.storage] && cache->W->clover[1] == f->C[DW_PREC_F64];
+  if (cache && !reuse) {
+    DW_CHECK_HIP(hipStreamSynchronize(stream));
+    destroy_cache(cache);
+    f->solver_cache = nullptr;
+    f->solver_cache_free = nullptr;
+    cache = nullptr;
+  }
   // RHS per batch: as many as fit in free device memory (at least one), at
   // most kMaxBatch (the per-RHS masks of a batch are 64 bits wide)
   size_t free_b = 0, total_b = 0;
@@ -650,19 +665,24 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
       free_b += (size_t)(res - used);
   }
   const size_t per = bytes_per_rhs(n, P->m, P->sap.storage, basis_prec(P), zstore_prec(P));
-  const bool reuse = graphs && cache && cache->W && cache->W->nr == nrhs && same_params(cache->W->P, *P) &&
-                     cache->W->clover[0] == f->C[P->sap.storage] && cache->W->clover[1] == f->C[DW_PREC_F64];
   int nb = (int)std::max<size_t>(1, (size_t)(0.9 * (double)free_b) / per);
   if (reuse || f->memory_reserved) nb = nrhs;
   nb = std::min(nb, (int)nrhs);
   nb = std::min(nb, kMaxBatch);
-  if (graphs && !reuse && cache) {
-    // parameters changed: the old workspace goes before the new one is made
-    DW_CHECK_HIP(hipStreamSynchronize(stream));
-    destroy_cache(cache);
-    f->solver_cache = nullptr;
-    f->solver_cache_free = nullptr;
-    cache = nullptr;
+  // The count misses memory that the stream-ordered allocator keeps from
+  // earlier solves (on this runtime its pool reports none reserved, yet the
+  // device shows it as used), so a batch of all right-hand sides is tried
+  // first; if it does not fit, the estimate stands.
+  std::unique_ptr<Work> whole;
+  if (nb < nrhs && nrhs <= kMaxBatch) {
+    whole = std::make_unique<Work>();
+    if (alloc_work(f, P, nrhs, *whole, stream) == DW_OK) {
+      nb = nrhs;
+    } else {
+      whole.reset();
+      (void)hipGetLastError();  // the failed allocation is not an error of this call
+      clear_error();
+    }
   }
   bool all_conv = true;
   std::vector<dw_solve_stats> st(nrhs);
@@ -676,6 +696,9 @@ extern "C" dw_status fgmresdr_solve(dw_field f, double m0, const fgmresdr_params
       W->P.max_iter = P->max_iter;
       W->P.tol = P->tol;
       W->P.restart_t = P->restart_t;
+    } else if (whole) {
+      own = std::move(whole);
+      W = own.get();
     } else {
       own = std::make_unique<Work>();
       DW_TRY(alloc_work(f, P, nr, *own, stream));

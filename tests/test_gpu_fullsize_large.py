@@ -1,0 +1,178 @@
+"""Parity at the two larger benchmark workloads, at their full sizes and in
+their launch configurations.
+
+* 32^3 x 64 with 12 right-hand sides in lock-step (point source + noise,
+  4^4 blocks): the FP64 operator on all 12 in one launch, compared at
+  sampled sites of every right-hand side with the oracle's operator
+  evaluated site by site (eq. 1); one SAP cycle (Alg. 2) on all 12 in one
+  launch, compared for three of them on the blocks of a window of the
+  lattice that the oracle's SAP gets exactly (see below).
+* 48^3 x 96 (8x4x4x4 blocks, FP16 SAP storage, s = 2, nMR = 5, FGMRES-DR
+  (30, 12), m0 = m_c(16^3x32) + 0.01): the operator at sampled sites, one SAP
+  cycle on the window's blocks, and the whole solve, whose final iterate is
+  checked with the oracle's operator (true residual at 1e-10).
+
+Window: the oracle runs SAP on a window of the lattice taken as a periodic
+lattice of its own. Blocks of colour 0 depend only on their own part of v
+(z starts at zero), so they are exact anywhere in the window; a block of
+colour 1 also reads the colour-0 result of its 8 neighbours, so it is exact
+when none of them wraps around the window's edge. The window's origin is a
+block corner with an even sum of block coordinates (the colours agree) and
+the window straddles the periodic boundary in several directions.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1204_5463_amd as P
+import synth
+from oracle import sap as S
+from oracle import wilson as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _crit(names, delta):
+    with open(os.path.join(HERE, "golden", "critical_mass.json")) as fh:
+        data = json.load(fh)
+    name = next(n for n in names if n in data)
+    return data[name]["m_c"] + delta
+
+
+def _window(a, shift, ext):
+    """Rolls a field with axes [..., t, z, y, x, ...] (two site-local axes
+    last) so that lattice site `shift` (x, y, z, t) moves to the origin and
+    returns the window of extents `ext` (x, y, z, t) there."""
+    lead = a.ndim - 6
+    out = a
+    for mu, s in enumerate(shift):
+        out = np.roll(out, -s, axis=lead + 3 - mu)
+    sl = [slice(None)] * out.ndim
+    for mu in range(4):
+        sl[lead + 3 - mu] = slice(0, ext[mu])
+    return out[tuple(sl)]
+
+
+def _window_sap_errors(U, v, z, m0, block, nmr, shift, ext):
+    """Relative errors of z (one SAP cycle of the GPU on the whole lattice)
+    on the window's colour-0 blocks and on its inner colour-1 blocks, against
+    the oracle's SAP run on the window."""
+    Uw = np.stack([_window(U[mu], shift, ext) for mu in range(4)])
+    vw = _window(v, shift, ext)
+    zo = S.sap(Uw, m0, ext, block, 1, nmr, vw)
+    zg = _window(z, shift, ext)
+    m0mask = S.colour_mask(ext, block, 0)
+    e0 = np.linalg.norm((zg - zo)[m0mask]) / np.linalg.norm(zo[m0mask])
+    # inner blocks: one block in from every window face (axes t, z, y, x)
+    inner = tuple(slice(block[mu], ext[mu] - block[mu]) for mu in (3, 2, 1, 0))
+    m1mask = S.colour_mask(ext, block, 1)[inner]
+    d = (zg - zo)[inner]
+    e1 = np.linalg.norm(d[m1mask]) / np.linalg.norm(zo[inner][m1mask])
+    return e0, e1
+
+
+def _sampled_sites(L, n, seed):
+    Lx, Ly, Lz, Lt = L
+    V = synth.volume(L)
+    rng = np.random.default_rng(seed)
+    return sorted(set(int(s) for s in rng.integers(0, V, n)) | {0, V - 1, Lx - 1, Lx * Ly * Lz * (Lt - 1)})
+
+
+# ---- 32^3 x 64 x 12 right-hand sides -------------------------------------------------
+
+L12, B12, NRHS = (32, 32, 32, 64), (4, 4, 4, 4), 12
+
+
+@pytest.fixture(scope="module")
+def multi(dwctx):
+    U = synth.gauge_field(L12, 0.7, 0)
+    f = P.Field(dwctx, L12, B12, P.to_device(U))
+    m0 = _crit(("32^3x64_eps0.7", "16^3x32_eps0.7", "12^4_eps0.7"), 0.005)
+    xs = np.stack([synth.point_source_noise(L12, j, 2000 + j) for j in range(NRHS)])
+    yield U, f, m0, xs
+    f.close()
+    torch.cuda.empty_cache()
+
+
+def test_multi_rhs_operator_sampled_sites(multi):
+    U, f, m0, xs = multi
+    print(f"32^3x64 x {NRHS} RHS: FP64 operator, one launch, m0={m0:.6f}", flush=True)
+    y = f.apply(m0, P.to_device(xs)).cpu().numpy().reshape(NRHS, -1, 4, 3)
+    sites = _sampled_sites(L12, 24, 1)
+    for j in range(NRHS):
+        ref = W.apply_D_at_sites(U, m0, xs[j], sites)
+        assert np.max(np.abs(y[j][sites] - ref)) < 1e-13 * np.max(np.abs(ref)), j
+
+
+@pytest.mark.parametrize("prec,tol", [(P.DW_PREC_F64, 1e-12), (P.DW_PREC_F16, 2e-2)])
+def test_multi_rhs_sap_window(multi, prec, tol):
+    U, f, m0, xs = multi
+    nmr = 8
+    print(f"32^3x64 x {NRHS} RHS: one SAP cycle, storage {prec}, one launch per colour", flush=True)
+    z = f.sap(m0, P.SapParams(block=B12, ncycles=1, nmr=nmr, storage=prec), P.to_device(xs)).cpu().numpy()
+    # window origin in blocks (7, 3, 1, 15): even sum; wraps in x and t
+    shift, ext = (28, 12, 4, 60), (16, 16, 16, 16)
+    for j in (0, 5, NRHS - 1):
+        e0, e1 = _window_sap_errors(U, xs[j], z[j], m0, B12, nmr, shift, ext)
+        assert e0 < tol and e1 < tol, (j, e0, e1)
+
+
+# ---- 48^3 x 96 ---------------------------------------------------------------------
+
+L48, B48 = (48, 48, 48, 96), (8, 4, 4, 4)
+
+
+@pytest.fixture(scope="module")
+def large(dwctx):
+    torch.cuda.empty_cache()
+    U = synth.gauge_field(L48, 0.7, 0)
+    f = P.Field(dwctx, L48, B48, P.to_device(U))
+    m0 = _crit(("16^3x32_eps0.7", "12^4_eps0.7"), 0.01)
+    yield U, f, m0
+    f.close()
+    torch.cuda.empty_cache()
+
+
+def test_large_operator_sampled_sites(large):
+    U, f, m0 = large
+    print(f"48^3x96: FP64 operator, m0={m0:.6f}", flush=True)
+    b = synth.gaussian_spinor(L48, 1000)
+    y = f.apply(m0, P.to_device(b)).cpu().numpy().reshape(-1, 4, 3)
+    sites = _sampled_sites(L48, 200, 2)
+    ref = W.apply_D_at_sites(U, m0, b, sites)
+    assert np.max(np.abs(y[sites] - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec,tol", [(P.DW_PREC_F64, 1e-12), (P.DW_PREC_F16, 2e-2)])
+def test_large_sap_window(large, prec, tol):
+    U, f, m0 = large
+    nmr = 5
+    print(f"48^3x96: one SAP cycle, 8x4x4x4 blocks, storage {prec}", flush=True)
+    v = synth.gaussian_spinor(L48, 1001)
+    z = f.sap(m0, P.SapParams(block=B48, ncycles=1, nmr=nmr, storage=prec), P.to_device(v)).cpu().numpy()
+    # window of 4^4 blocks, origin in blocks (5, 3, 11, 23): even sum; wraps in x, z and t
+    shift, ext = (40, 12, 44, 92), (32, 16, 16, 16)
+    e0, e1 = _window_sap_errors(U, v, z, m0, B48, nmr, shift, ext)
+    assert e0 < tol and e1 < tol, (e0, e1)
+
+
+def test_large_solve_true_residual(large):
+    U, f, m0 = large
+    b = synth.gaussian_spinor(L48, 1000)
+    prm = P.SolverParams(m=30, k=12, max_iter=2000, tol=1e-10,
+                         sap=P.SapParams(block=B48, ncycles=2, nmr=5, storage=P.DW_PREC_F16))
+    print("48^3x96: FGMRES-DR(30, 12), FP16 SAP s=2 nMR=5", flush=True)
+    x, st = f.solve(m0, prm, P.to_device(b))
+    print(f"48^3x96 solve: {st[0].iterations} it, {st[0].cycles} cycles, {st[0].clean_restarts} clean restarts",
+          flush=True)
+    assert st[0].converged and st[0].true_relres <= 1e-10
+    assert st[0].cycles >= 3  # several deflated restarts at the configured (30, 12)
+    x = x.cpu().numpy()
+    torch.cuda.empty_cache()
+    r = b - W.apply_D(U, m0, x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)

@@ -73,6 +73,37 @@ def test_cycle_graphs_equal_eager(field, flags, nrhs, shared):
         assert np.array_equal(xe.cpu().numpy(), xg.cpu().numpy()), i
 
 
+def test_kept_workspace_serves_a_timed_solve(field):
+    """A solve with per-kernel timing on (so without graphs) after a captured
+    solve of the same shape runs in the workspace the captured solve kept:
+    one lock-step batch for the three right-hand sides, the same iterations
+    and the same iterate bit for bit; the captured cycles then replay again."""
+    U, f = field
+    st = torch.cuda.Stream()
+    nrhs, m0 = 3, MC + 0.03
+    b = synth.gaussian_spinors(L, nrhs, seed0=1010)
+    prm = _prm(flags=P.SOLVE_GRAPHS)
+    with torch.cuda.stream(st):
+        bd = P.to_device(b)
+        xg, sg = f.solve(m0, prm, bd, stream=st)
+        st.synchronize()
+        f.ctx.profile_reset()
+        f.ctx.profile(True)
+        xp, sp = f.solve(m0, prm, bd, stream=st)
+        f.ctx.profile(False)
+        sap = f.ctx.profile_stats()["sap"]["launches"]
+        xg2, sg2 = f.solve(m0, prm, bd, stream=st)
+    st.synchronize()
+    its = [s.iterations for s in sg]
+    assert all(s.converged for s in sg) and [s.iterations for s in sp] == its == [s.iterations for s in sg2]
+    assert np.array_equal(xg.cpu().numpy(), xp.cpu().numpy())
+    assert np.array_equal(xg.cpu().numpy(), xg2.cpu().numpy())
+    # SAP (one cycle: two colour launches per Arnoldi step) covered all three
+    # right-hand sides per launch, not one batch after another
+    print(f"timed solve after a captured one: iterations {its}, {sap} SAP launches", flush=True)
+    assert 2 * max(its) <= sap < 2 * sum(its)
+
+
 def test_solution_of_graph_solve_is_right(field):
     """The replayed solve reaches the 1e-10 true residual by the oracle's D."""
     U, f = field
