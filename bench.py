@@ -539,7 +539,7 @@ def main():
     ap.add_argument("--study-iters", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU volume split is a design, not built", file=sys.stderr)
         sys.exit(2)
     if args.serve:
