@@ -759,6 +759,7 @@ def main():
             out_extra[key] = {"solves_per_s": round(nrhs / t32, 4),
                               "iterations": max(s.iterations for s in s32),
                               "cycles": max(s.cycles for s in s32),
+                              "clean_restarts": max(s.clean_restarts for s in s32),
                               "true_relres": max(s.true_relres for s in s32)}
     # ---- the same solve with each SAP storage precision
     if args.all_precisions:
