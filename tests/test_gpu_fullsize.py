@@ -69,6 +69,22 @@ def test_sap_full_size_sampled_blocks(big, prec, tol):
     mask0 = S.colour_mask((16, 16, 16, 16), B, 0)
     e0 = np.linalg.norm((zg - zo)[mask0]) / np.linalg.norm(zo[mask0])
     assert e0 < tol, e0
+    if prec == P.DW_PREC_F16:
+        # element by element against the oracle on the same FP16-rounded links
+        # and RMS-scaled input, with the bound 2 u (nmr + 1) (|ref| + rms(ref))
+        # of the 8^4 element-wise test, on the window's exact blocks
+        def r16(a):
+            return a.real.astype(np.float16).astype(np.float64) + 1j * a.imag.astype(np.float16).astype(np.float64)
+        sigma = np.sqrt(v.size / np.vdot(v, v).real)
+        ref = S.sap(r16(Uw), m0, (16, 16, 16, 16), B, 1, nmr, r16(sigma * vw)) / sigma
+        inner_m = np.zeros(mask0.shape, dtype=bool)
+        inner_m[inner] = True
+        exact = mask0 | (inner_m & S.colour_mask((16, 16, 16, 16), B, 1))
+        r = ref[exact]
+        bound = 2 * 2.0 ** -11 * (nmr + 1) * (np.abs(r) + np.sqrt(np.mean(np.abs(r) ** 2)))
+        ratio = float((np.abs(zg[exact] - r) / bound).max())
+        print(f"32^3x64 FP16 SAP element-wise max error / bound = {ratio:.3f}", flush=True)
+        assert ratio <= 1.0, ratio
 
 
 @pytest.mark.parametrize("flags", [0, P.SOLVE_V32, P.SOLVE_A32 | P.SOLVE_INJECT])

@@ -6,7 +6,9 @@ their launch configurations.
   sampled sites of every right-hand side with the oracle's operator
   evaluated site by site (eq. 1); one SAP cycle (Alg. 2) on all 12 in one
   launch, compared for three of them on the blocks of a window of the
-  lattice that the oracle's SAP gets exactly (see below).
+  lattice that the oracle's SAP gets exactly (see below); with FP16
+  storage also element by element against the oracle run on the same
+  FP16-rounded links and input.
 * 48^3 x 96 (8x4x4x4 blocks, FP16 SAP storage, s = 2, nMR = 5, FGMRES-DR
   (30, 12), m0 = m_c(16^3x32) + 0.01): the operator at sampled sites, one SAP
   cycle on the window's blocks, and the whole solve, whose final iterate is
@@ -76,6 +78,31 @@ def _window_sap_errors(U, v, z, m0, block, nmr, shift, ext):
     return e0, e1
 
 
+def _round16(z):
+    """FP64 -> FP16 (to nearest even) -> FP64, real and imaginary parts."""
+    return z.real.astype(np.float16).astype(np.float64) + 1j * z.imag.astype(np.float16).astype(np.float64)
+
+
+def _window_sap_fp16_ratio(U, v, z, m0, block, nmr, shift, ext):
+    """FP16 storage, element by element: the oracle's SAP on the window with
+    the links and the RMS-scaled input rounded to FP16 as the library stores
+    them (SAP is scale-equivariant), on the window's exact blocks, against
+    the bound 2 u (nmr + 1) (|ref| + rms(ref)), u = 2^-11, derived for one
+    cycle of 16-bit block solves (each of the nmr + 1 block-operator
+    applications carries about 2u of its magnitude). Returns max error / bound."""
+    sigma = np.sqrt(v.size / np.vdot(v, v).real)
+    Uw = np.stack([_window(U[mu], shift, ext) for mu in range(4)])
+    vw = _window(v, shift, ext)
+    ref = S.sap(_round16(Uw), m0, ext, block, 1, nmr, _round16(sigma * vw)) / sigma
+    zg = _window(z, shift, ext)
+    inner = np.zeros(S.colour_mask(ext, block, 0).shape, dtype=bool)
+    inner[tuple(slice(block[mu], ext[mu] - block[mu]) for mu in (3, 2, 1, 0))] = True
+    exact = S.colour_mask(ext, block, 0) | (inner & S.colour_mask(ext, block, 1))
+    r = ref[exact]
+    tol = 2 * 2.0 ** -11 * (nmr + 1) * (np.abs(r) + np.sqrt(np.mean(np.abs(r) ** 2)))
+    return float((np.abs(zg[exact] - r) / tol).max())
+
+
 def _sampled_sites(L, n, seed):
     Lx, Ly, Lz, Lt = L
     V = synth.volume(L)
@@ -120,6 +147,10 @@ def test_multi_rhs_sap_window(multi, prec, tol):
     for j in (0, 5, NRHS - 1):
         e0, e1 = _window_sap_errors(U, xs[j], z[j], m0, B12, nmr, shift, ext)
         assert e0 < tol and e1 < tol, (j, e0, e1)
+        if prec == P.DW_PREC_F16:
+            ratio = _window_sap_fp16_ratio(U, xs[j], z[j], m0, B12, nmr, shift, ext)
+            print(f"RHS {j}: FP16 element-wise max error / bound = {ratio:.3f}", flush=True)
+            assert ratio <= 1.0, (j, ratio)
 
 
 # ---- 48^3 x 96 ---------------------------------------------------------------------
@@ -159,6 +190,10 @@ def test_large_sap_window(large, prec, tol):
     shift, ext = (40, 12, 44, 92), (32, 16, 16, 16)
     e0, e1 = _window_sap_errors(U, v, z, m0, B48, nmr, shift, ext)
     assert e0 < tol and e1 < tol, (e0, e1)
+    if prec == P.DW_PREC_F16:
+        ratio = _window_sap_fp16_ratio(U, v, z, m0, B48, nmr, shift, ext)
+        print(f"48^3x96 FP16 element-wise max error / bound = {ratio:.3f}", flush=True)
+        assert ratio <= 1.0, ratio
 
 
 def test_large_solve_true_residual(large):
